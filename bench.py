@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the bosonic PIMD step on one MI355X.
+
+Workload: N=1600 Gaussian-interacting bosons in a 2-D harmonic trap, P=32 beads, beta=3,
+xi=1, A=0.5, s=0.5 (hbar = m = omega = 1), seeded positions N(0, 2^2), Maxwell-Boltzmann
+momenta, massive Nose-Hoover chains of length 4, dt=0.01.  A step is one full MD step:
+thermostat and integrator halves, all-pairs forces of every slice, springs and trap, the
+forward and backward exchange recursions, connection probabilities and end-bead forces.
+
+Reported: aggregate replica-steps/s of the mixed-precision batched path (R replicas of the
+workload, seeds 303+r, in one context), the plain FP64 single-replica path beside it, the
+bead-updates/s (= steps/s * sum_r N P), the roofline of the dominant kernel (per-launch HIP
+events on the stream it runs on), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2404_02628_amd.workloads import WORKLOADS, initial_state  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (published)
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (published)
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E (published)
+
+
+def make_ctx(precision, R, nhc_len=4):
+    from paper_2404_02628_amd.pimd import Context
+    base = WORKLOADS["large_gauss"]
+    systems = [base.with_(seed=base.seed + r) for r in range(R)]
+    ctx = Context(systems, precision=precision, nhc_len=nhc_len, density_bins=64, density_rmax=8.0,
+                  trace_capacity=0)
+    for r, s in enumerate(systems):
+        x, p = initial_state(s)
+        ctx.set_state(r, x, p)
+    return ctx, systems
+
+
+def timed_steps(ctx, steps):
+    import torch
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps, 0)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_path(precision, R, steps, warmup):
+    ctx, systems = make_ctx(precision, R)
+    try:
+        ctx.step(warmup, 0)
+        dt = timed_steps(ctx, steps)
+    finally:
+        ctx.close()
+    return dt, systems
+
+
+def kernel_profile(precision, R, steps):
+    """Per-kernel average launch time from HIP events bracketing each launch on its stream."""
+    ctx, systems = make_ctx(precision, R)
+    try:
+        ctx.step(5, 0)
+        ctx.profile(True)
+        ctx.step(steps, 0)
+        times = ctx.kernel_times()
+        ctx.profile(False)
+    finally:
+        ctx.close()
+    return times, systems
+
+
+def algorithmic_work(kind, systems, P, D):
+    """(bound, units per launch, work per unit, unit name, peak) for one kernel kind."""
+    npairs = sum(P * s.n * s.n for s in systems if s.pair_amp > 0)  # ordered pairs incl. self
+    tri = sum(s.n * (s.n + 1) // 2 for s in systems)
+    dofs = sum(D * P * s.n for s in systems)
+    if kind == "pair":
+        # per ordered pair: D subtractions, D FMAs (|dr|^2), one exp, D FMAs (force) = 5D + 1 flops
+        return "alu", npairs, 5 * D + 1, "TFLOP/s", PEAK_FP32_TFLOPS
+    if kind == "recursion":
+        # two recursions, each N(N+1)/2 log-sum-exp terms: distance (3D) + 6 adds + exp (~20) ~ 30 flops
+        return "alu", 2 * tri, 3 * D + 26, "TFLOP/s", PEAK_FP64_TFLOPS
+    if kind == "probs":
+        return "alu", tri, 8 * D + 24, "TFLOP/s", PEAK_FP64_TFLOPS
+    if kind in ("springs",):
+        # read x, write f (8 B each per dof), plus end beads / links per particle (small)
+        return "hbm", dofs, 16, "GB/s", PEAK_HBM_GBS
+    if kind == "integrate_first":
+        # x, p, f, eta[4], veta[4] read; x, p, eta, veta written
+        return "hbm", dofs, 8 * (11 + 10), "GB/s", PEAK_HBM_GBS
+    if kind == "integrate_second":
+        return "hbm", dofs, 8 * (11 + 9), "GB/s", PEAK_HBM_GBS
+    return "hbm", dofs, 8, "GB/s", PEAK_HBM_GBS
+
+
+def cpu_baseline(sample_steps=12):
+    """The CPU oracle as it stands (sequential FP64, one thread) on a bounded sample."""
+    import oracle
+    s = WORKLOADS["large_gauss"]
+    par = oracle.OracleParams(n=s.n, p=s.p, dim=s.dim, beta=s.beta, xi=s.xi, pair_amp=s.pair_amp,
+                              pair_width=s.pair_width)
+    md = oracle.OracleMD(dt=s.dt, nhc_len=4)
+    x, p = initial_state(s)
+    f, _ = oracle.compute_forces(par, x)
+    eta = np.zeros((4,) + x.shape)
+    veta = np.zeros_like(eta)
+    t0 = time.perf_counter()
+    oracle.step(par, md, x, p, eta, veta, f, sample_steps)
+    dt = time.perf_counter() - t0
+    return {"value": sample_steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample_steps} full MD steps of one N=1600, P=32 replica (sequential FP64 C oracle)"}
+
+
+def energy_precision_error():
+    """Mixed vs FP64 estimator on the same configuration (the precision-induced error)."""
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ctx, _ = make_ctx(prec, 1)
+        try:
+            ctx.compute_forces()
+            out[prec] = ctx.energies(0)
+        finally:
+            ctx.close()
+    rel = {k: abs(out["mixed"][k] - out["fp64"][k]) / max(abs(out["fp64"][k]), 1e-300)
+           for k in ("e_prim", "e_vir", "u_pair", "v_exch")}
+    return rel
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--replicas", type=int, default=0, help="0 = choose by a short sweep")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(replicas and slices would shard over GPUs, see DESIGN.md); use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    base = WORKLOADS["large_gauss"]
+    P, D = base.p, base.dim
+
+    # plain FP64 path: one replica
+    t64, _ = run_path("fp64", 1, args.steps, args.warmup)
+    fp64_sps = args.steps / t64
+
+    # mixed batched: choose R by a short sweep unless given
+    if args.replicas > 0:
+        R = args.replicas
+    else:
+        best, R = 0.0, 1
+        for r in (1, 4, 8, 16, 32, 64):
+            n = max(20, args.steps // 10)
+            t, _ = run_path("mixed", r, n, 5)
+            rate = r * n / t
+            if rate > best:
+                best, R = rate, r
+    tmix, systems = run_path("mixed", R, args.steps, args.warmup)
+    sps = R * args.steps / tmix
+    beads = sum(s.n * s.p for s in systems)
+
+    # roofline of the dominant kernel of the mixed batched step
+    times, systems = kernel_profile("mixed", R, max(20, min(args.steps, 100)))
+    dom = max(times.items(), key=lambda kv: kv[1][0])
+    kind, (ms_total, launches) = dom[0], dom[1]
+    avg_s = ms_total / max(launches, 1) / 1e3
+    bound, units, per_unit, unit, peak = algorithmic_work(kind, systems, P, D)
+    achieved = units * per_unit / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
+    kernels = {k: {"avg_us": v[0] / max(v[1], 1) * 1e3, "launches": v[1], "total_ms": v[0]}
+               for k, v in times.items() if v[1] > 0}
+
+    rel = energy_precision_error()
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    rec = {
+        "metric": "PIMD steps/s & bead-updates/s at N=1600,P=32: mixed vs FP64 at <=0.2% energy error",
+        "value": sps,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tmix / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "large_gauss: N=1600 bosons, 2-D trap, P=32, beta=3, A=0.5, s=0.5, mixed precision",
+                   "replicas": R, "global_batch": R, "beads": P, "particles": base.n,
+                   "parallelism": "replica batching on 1 GPU"},
+        "bead_updates_per_s": sps * beads / R,
+        "fp64_single_steps_per_s": fp64_sps,
+        "fp64_single_bead_updates_per_s": fp64_sps * base.n * base.p,
+        "speedup_mixed_batched_vs_fp64": sps / fp64_sps,
+        "energy_rel_err_mixed_vs_fp64_same_config": rel,
+        "roofline": {"kernel": kind, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": None},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * pimd.h -- C ABI of libpimd, an MI355X (gfx950) library for bosonic and
+ * fictitious-particle path integral molecular dynamics (PIMD).
+ *
+ * Method: Y. Xiong, "GPU acceleration of ab initio simulations of large-scale
+ * identical particles based on path integral molecular dynamics",
+ * arXiv:2404.02628.  N identical particles, each a ring polymer of P beads in
+ * d dimensions, sampled with weight exp(-beta (V_xi^{[1,N]} + U/P)) (Sec. II,
+ * Eq. 4).  U is the trap plus Gaussian pair energy of every imaginary-time
+ * slice (Eqs. 5, 19, 20); V_xi^{[1,N]} is the exchange potential of Eq. 6,
+ * built from the cycle spring energies of Eqs. 7-10; its gradient comes from
+ * the backward potentials and connection probabilities of Eqs. 11-17.  The
+ * exchange parameter xi is 1 for bosons, 0 for distinguishable particles and
+ * in (0,1) for fictitious identical particles (Sec. II).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a pimd_status; nothing throws across the ABI.  On
+ *   failure pimd_last_error() returns a thread-local, library-owned message
+ *   that stays valid until the next call on the same thread.
+ * - Coordinates, momenta and forces of one replica are double arrays in the
+ *   layout [dim][P][N]: element ((a*P + j)*N + l) is component a of bead j
+ *   (0-based) of particle l (0-based).
+ * - Device memory: the caller allocates ONE device workspace of
+ *   pimd_workspace_bytes() bytes (for example a torch uint8 CUDA tensor) and
+ *   passes it to pimd_create; the library never allocates device memory.
+ *   The workspace and the stream are borrowed: they must outlive the context.
+ * - Streams: work is enqueued on the caller's HIP stream (hipStream_t passed
+ *   as void*; NULL selects the default stream).  pimd_compute_forces and
+ *   pimd_step only enqueue; getters that return data synchronise the stream.
+ * - A context is not thread-safe.  Contexts are independent of each other.
+ * - Arguments that are invalid (bad sizes, NULL where not allowed, replica
+ *   index out of range, parameters outside their domain) give
+ *   PIMD_ERR_INVALID and leave the context unchanged.  HIP runtime failures
+ *   give PIMD_ERR_DEVICE.
+ */
+#ifndef PIMD_H
+#define PIMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIMD_ABI_VERSION 1
+
+typedef enum {
+    PIMD_OK = 0,
+    PIMD_ERR_INVALID = -1,    /* invalid argument; nothing changed                         */
+    PIMD_ERR_DEVICE = -2,     /* HIP runtime error (message in pimd_last_error)            */
+    PIMD_ERR_NONFINITE = -3,  /* a force or energy of some replica is not finite           */
+    PIMD_ERR_WORKSPACE = -4,  /* workspace NULL, misaligned (256 B) or smaller than needed */
+    PIMD_ERR_STATE = -5       /* call out of order (e.g. energies before any evaluation)   */
+} pimd_status;
+
+typedef enum {
+    PIMD_FP64 = 0,   /* every quantity in double precision                                   */
+    PIMD_MIXED = 1   /* pair distances, Gaussian terms and pair forces in FP32 (per-tile FP32
+                        partials folded into FP64); springs, recursions, probabilities,
+                        thermostat and all reductions in FP64                                  */
+} pimd_precision;
+
+typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
+
+/* One independent system (replica).  Units are free; the paper uses
+ * hbar = m = omega = k_B = 1 (Sec. IV.A). */
+typedef struct {
+    int32_t n;            /* particles, N >= 1                                               */
+    int32_t reserved;     /* must be 0                                                       */
+    double beta;          /* inverse temperature > 0                                         */
+    double hbar;          /* > 0                                                             */
+    double mass;          /* particle mass m > 0; spring constant m omega_P^2, omega_P = sqrt(P)/(beta hbar) (Sec. III) */
+    double omega;         /* trap frequency >= 0: U_trap = (1/2) m omega^2 r^2 per bead (Eq. 19) */
+    double xi;            /* exchange parameter, 0 <= xi <= 1 (the probabilities of Eqs. 12-14 need xi >= 0) */
+    double pair_amp;      /* Gaussian amplitude A >= 0: A exp(-|r_i - r_j|^2 / s^2) per unordered pair (Eq. 20) */
+    double pair_width;    /* s > 0 (ignored when A == 0)                                     */
+    double dt;            /* MD time step > 0                                                */
+    double nhc_q;         /* thermostat mass Q; <= 0 selects 1/(beta omega_P^2)              */
+    double bead_mass;     /* fictitious bead mass m'; <= 0 selects the particle mass         */
+} pimd_replica;
+
+typedef struct {
+    int32_t n_replicas;      /* >= 1                                                         */
+    int32_t p;               /* beads per ring, P >= 2 (Eqs. 15-16 need distinct end beads)  */
+    int32_t dim;             /* 1, 2 or 3                                                    */
+    int32_t precision;       /* pimd_precision                                               */
+    int32_t nhc_len;         /* Nose-Hoover chain length per degree of freedom, 0..8 (0 = NVE) */
+    int32_t sy_order;        /* Suzuki-Yoshida order of the thermostat step: 1, 3 or 5       */
+    int32_t density_bins;    /* radial density bins >= 1 (one extra overflow bin is kept)    */
+    int32_t trace_capacity;  /* energy samples kept per replica (ring buffer), >= 0          */
+    double density_rmax;     /* radius covered by the bins > 0                               */
+    const pimd_replica* replicas; /* n_replicas entries, copied by pimd_create              */
+} pimd_config;
+
+/* Estimators of one evaluation (Sec. IV reports energies and densities). */
+typedef struct {
+    double v_exch;         /* V_xi^{[1,N]} (Eq. 6 at n = N)                                     */
+    double u_trap;         /* trap part of U = sum_j V(slice j) (Eqs. 5, 19)                    */
+    double u_pair;         /* pair part of U (Eq. 20, each unordered pair once)                 */
+    double spring_expect;  /* S = sum_{l'<=l} Pr[l->l'] E^{[l',l]}: expected spring energy      */
+    double virial;         /* sum_j [U_j + (1/2) sum_l r_l^j . grad U_j]                        */
+    double e_prim;         /* primitive estimator d N P/(2 beta) - S + U/P                       */
+    double e_vir;          /* origin-virial estimator virial / P                                 */
+    double kinetic;        /* sum p^2/(2 m') over all bead coordinates                           */
+    double nhc_energy;     /* sum over chains of Q v^2/2 + eta/beta                              */
+    double h_conserved;    /* kinetic + V_xi + U/P + nhc_energy: conserved by the dynamics       */
+    int64_t step;          /* MD step count at which the values were taken                       */
+} pimd_estimates;
+
+typedef struct pimd_ctx pimd_ctx;
+
+/* ABI version of the loaded library (PIMD_ABI_VERSION at build time). */
+int pimd_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none). Library-owned. */
+const char* pimd_last_error(void);
+
+/* Bytes of device workspace that pimd_create needs for `cfg` (written to *bytes).
+ * Validates cfg like pimd_create.  Errors: PIMD_ERR_INVALID. */
+pimd_status pimd_workspace_bytes(const pimd_config* cfg, size_t* bytes);
+
+/* Creates a context on the current HIP device.  d_workspace: device pointer,
+ * 256-byte aligned, at least pimd_workspace_bytes(cfg) bytes, owned by the
+ * caller.  hip_stream: hipStream_t (or NULL).  Copies cfg and its replicas.
+ * All replicas start at x = p = 0 with zeroed thermostats and accumulators.
+ * Errors: PIMD_ERR_INVALID, PIMD_ERR_WORKSPACE, PIMD_ERR_DEVICE. */
+pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
+                        void* hip_stream, pimd_ctx** out);
+
+/* Destroys the host-side context (synchronises its stream first).  NULL is a no-op. */
+pimd_status pimd_destroy(pimd_ctx* ctx);
+
+/* Sets positions x and (optionally) momenta p of replica r, layout [dim][P][N].
+ * nhc (optional) holds the thermostat state as [2][nhc_len][dim][P][N]
+ * (positions eta, then velocities v_eta); NULL zeroes it (p NULL zeroes p).
+ * `where` says whether the pointers are host or device memory.  Invalidates the
+ * forces of replica r until the next evaluation.  Synchronous. */
+pimd_status pimd_set_state(pimd_ctx* ctx, int32_t r, const double* x, const double* p,
+                           const double* nhc, pimd_mem where);
+
+/* Copies the state of replica r out (any pointer may be NULL).  Synchronous. */
+pimd_status pimd_get_state(pimd_ctx* ctx, int32_t r, double* x, double* p, double* nhc,
+                           pimd_mem where);
+
+/* One force-and-energy evaluation of every replica at its current positions:
+ * pair and trap forces (Eqs. 5, 20), cycle energies (Eqs. 7-10), forward and
+ * backward exchange potentials (Eqs. 6, 11), connection probabilities (Eqs.
+ * 12-14), exchange forces (Eqs. 15-17) and all estimators.  Enqueued only. */
+pimd_status pimd_compute_forces(pimd_ctx* ctx);
+
+/* Total force -grad(V_xi + U/P) of replica r from the last evaluation, layout
+ * [dim][P][N].  Synchronises.  Errors: PIMD_ERR_STATE if never evaluated. */
+pimd_status pimd_get_forces(pimd_ctx* ctx, int32_t r, double* f, pimd_mem where);
+
+/* Advances every replica by n_steps velocity-Verlet steps with massive
+ * Nose-Hoover chains at k_B T = 1/beta (Sec. IV.A): NHC(dt/2), p += F dt/2,
+ * x += p dt/m', F = force(x), p += F dt/2, NHC(dt/2).  The estimators, the
+ * density histogram and the trace are taken every `sample_every` steps
+ * (0 = never).  The first call evaluates the forces of the initial state.
+ * Enqueued only.  Errors: PIMD_ERR_INVALID (n_steps < 0, sample_every < 0). */
+pimd_status pimd_step(pimd_ctx* ctx, int64_t n_steps, int32_t sample_every);
+
+/* Estimators of replica r from its most recent sampled evaluation (every
+ * pimd_compute_forces samples).  Synchronises.  Errors: PIMD_ERR_STATE if none
+ * yet; PIMD_ERR_NONFINITE if a value is not finite (values still written). */
+pimd_status pimd_energies(pimd_ctx* ctx, int32_t r, pimd_estimates* out);
+
+/* Copies up to max_samples most recent trace records of replica r (oldest
+ * first) into out (host, pimd_estimates array); *n_samples receives the count
+ * written.  Synchronises. */
+pimd_status pimd_trace(pimd_ctx* ctx, int32_t r, pimd_estimates* out, int64_t max_samples,
+                       int64_t* n_samples);
+
+/* Radial density histogram of replica r over all N*P beads of every sample:
+ * counts[b] for |r| in [b, b+1) * rmax/bins, counts[bins] for |r| >= rmax
+ * (host array of bins+1).  *n_samples receives the number of samples.  The
+ * normalised density of Sec. IV.A is counts / (n_samples N P shell_b).
+ * Synchronises. */
+pimd_status pimd_density(pimd_ctx* ctx, int32_t r, uint64_t* counts, int64_t* n_samples);
+
+/* Clears the trace and density accumulators of every replica. Enqueued. */
+pimd_status pimd_reset_accumulators(pimd_ctx* ctx);
+
+/* Exchange potentials of replica r from the last evaluation (host arrays):
+ * X[n] = beta V^{[1,n]} for n = 0..N (Eq. 6, X[0] = 0) and Y[u] = beta V^{[u,N]}
+ * for u = 1..N+1 (Eq. 11, Y[N+1] = 0; Y[0] is set to 0).  Synchronises. */
+pimd_status pimd_debug_potentials(pimd_ctx* ctx, int32_t r, double* X, double* Y);
+
+/* Dense connection probabilities of replica r (Eqs. 12-14) from the last
+ * evaluation: G[(l-1)*N + (l'-1)] = Pr[G(l) = l'] (host array of N*N doubles).
+ * Intended for tests at small N; recomputes the entries.  Synchronises. */
+pimd_status pimd_debug_probs(pimd_ctx* ctx, int32_t r, double* G);
+
+/* Per-kernel timing with HIP events on the stream each kernel is launched
+ * on.  pimd_profile(ctx, 1) clears and enables, 0 disables.  pimd_kernel_times
+ * synchronises and writes, for up to max_kinds kernel kinds, the summed
+ * milliseconds and the launch counts; *n_kinds receives the number of kinds.
+ * pimd_kernel_name(k) names kind k. */
+pimd_status pimd_profile(pimd_ctx* ctx, int enable);
+pimd_status pimd_kernel_times(pimd_ctx* ctx, double* ms, int64_t* launches, int32_t max_kinds,
+                              int32_t* n_kinds);
+const char* pimd_kernel_name(int32_t kind);
+
+/* Waits for all work enqueued by the context. */
+pimd_status pimd_synchronize(pimd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIMD_H */

@@ -1,0 +1,612 @@
+// capi.hip -- C ABI of libpimd: validation, workspace plan, per-step launch order.
+//
+// A force evaluation of all replicas is, in order on the caller's stream:
+//   springs (interior/trap forces, end beads, links, E_int, FP32 shadow)
+//   -> [pair kernel on a second stream, joined before the integrator]
+//   -> forward+backward exchange recursion -> probability tiles -> per-particle reduction
+//      (end-bead forces, expected spring energy)
+// and an MD step wraps it in the two halves of the thermostatted velocity-Verlet step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pimd.h"
+#include "pimd_internal.h"
+
+using namespace pimd;
+
+namespace {
+
+thread_local std::string g_err;
+
+pimd_status fail(pimd_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(PIMD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+enum Kind { K_SPRINGS = 0, K_PAIR, K_RECURSION, K_PROBS, K_REDUCE, K_INT1, K_INT2, K_EST, K_DENS, K_COUNT };
+const char* kKindNames[K_COUNT] = {"springs", "pair", "recursion", "probs", "probs_reduce",
+                                   "integrate_first", "integrate_second", "estimators", "density"};
+
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+struct Plan {
+  Dims d{};
+  int jsplit = 1;
+  std::vector<RepDev> reps;
+  std::vector<int4> springwork, pairwork, probwork;
+  size_t off[32]{};
+  size_t total = 0;
+};
+
+enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LINK, S_EINT, S_GF, S_GB, S_ROWP,
+           S_COLP, S_SPRINGP, S_PAIRP, S_REDP, S_REC, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_SPRINGW, S_PAIRW,
+           S_PROBW, S_DBG, S_COUNT };
+
+pimd_status validate(const pimd_config* c) {
+  if (!c) return fail(PIMD_ERR_INVALID, "config is NULL");
+  if (c->n_replicas < 1) return fail(PIMD_ERR_INVALID, "n_replicas must be >= 1");
+  if (!c->replicas) return fail(PIMD_ERR_INVALID, "replicas is NULL");
+  if (c->p < 2) return fail(PIMD_ERR_INVALID, "P must be >= 2");
+  if (c->p > 4096) return fail(PIMD_ERR_INVALID, "P must be <= 4096");
+  if (c->dim < 1 || c->dim > 3) return fail(PIMD_ERR_INVALID, "dim must be 1, 2 or 3");
+  if (c->precision != PIMD_FP64 && c->precision != PIMD_MIXED) return fail(PIMD_ERR_INVALID, "bad precision");
+  if (c->nhc_len < 0 || c->nhc_len > kMaxNhc) return fail(PIMD_ERR_INVALID, "nhc_len must be in 0..8");
+  if (c->sy_order != 1 && c->sy_order != 3 && c->sy_order != 5) return fail(PIMD_ERR_INVALID, "sy_order must be 1, 3 or 5");
+  if (c->density_bins < 1 || c->density_bins > 4096) return fail(PIMD_ERR_INVALID, "density_bins must be in 1..4096");
+  if (!(c->density_rmax > 0)) return fail(PIMD_ERR_INVALID, "density_rmax must be > 0");
+  if (c->trace_capacity < 0) return fail(PIMD_ERR_INVALID, "trace_capacity must be >= 0");
+  for (int r = 0; r < c->n_replicas; ++r) {
+    const pimd_replica& q = c->replicas[r];
+    std::string where = "replica " + std::to_string(r) + ": ";
+    if (q.n < 1 || q.n > (1 << 20)) return fail(PIMD_ERR_INVALID, where + "n must be in 1..2^20");
+    if (q.reserved != 0) return fail(PIMD_ERR_INVALID, where + "reserved must be 0");
+    if (!(q.beta > 0) || !std::isfinite(q.beta)) return fail(PIMD_ERR_INVALID, where + "beta must be > 0");
+    if (!(q.hbar > 0) || !std::isfinite(q.hbar)) return fail(PIMD_ERR_INVALID, where + "hbar must be > 0");
+    if (!(q.mass > 0) || !std::isfinite(q.mass)) return fail(PIMD_ERR_INVALID, where + "mass must be > 0");
+    if (!(q.omega >= 0) || !std::isfinite(q.omega)) return fail(PIMD_ERR_INVALID, where + "omega must be >= 0");
+    if (!(q.xi >= 0 && q.xi <= 1)) return fail(PIMD_ERR_INVALID, where + "xi must be in [0, 1]");
+    if (!(q.pair_amp >= 0) || !std::isfinite(q.pair_amp)) return fail(PIMD_ERR_INVALID, where + "pair_amp must be >= 0");
+    if (q.pair_amp > 0 && (!(q.pair_width > 0) || !std::isfinite(q.pair_width)))
+      return fail(PIMD_ERR_INVALID, where + "pair_width must be > 0");
+    if (!(q.dt > 0) || !std::isfinite(q.dt)) return fail(PIMD_ERR_INVALID, where + "dt must be > 0");
+    if (!std::isfinite(q.nhc_q) || !std::isfinite(q.bead_mass)) return fail(PIMD_ERR_INVALID, where + "non-finite nhc_q/bead_mass");
+  }
+  return PIMD_OK;
+}
+
+void make_plan(const pimd_config* c, Plan& pl) {
+  Dims& d = pl.d;
+  d.R = c->n_replicas; d.P = c->p; d.D = c->dim; d.M = c->nhc_len; d.precision = c->precision;
+  d.sy_order = c->sy_order; d.bins = c->density_bins; d.cap = c->trace_capacity; d.rmax = c->density_rmax;
+  const int dp = shadow_dp(d.D);
+  // pair split: enough waves to cover the machine (256 CUs x 4 SIMDs x ~2)
+  long long tiles64 = 0;
+  for (int r = 0; r < d.R; ++r)
+    if (c->replicas[r].pair_amp > 0) tiles64 += (long long)d.P * ((c->replicas[r].n + 63) / 64);
+  pl.jsplit = tiles64 < 1024 ? 4 : (tiles64 < 2048 ? 2 : 1);
+  const int ipw = 64 * (4 / pl.jsplit);  // particles per pair workgroup
+  long long G = 0, NP = 0, PROB = 0, XS = 0;
+  int maxn = 0;
+  pl.reps.resize(d.R);
+  for (int r = 0; r < d.R; ++r) {
+    const pimd_replica& q = c->replicas[r];
+    RepDev& R = pl.reps[r];
+    std::memset(&R, 0, sizeof(R));
+    R.n = q.n;
+    R.npad = (int)round_up(q.n, kTile);
+    R.npp = R.npad + kTile;
+    R.nblk = (q.n + kTile - 1) / kTile;
+    R.ndof = (long long)d.D * d.P * q.n;
+    R.dof = G;
+    G += round_up(R.ndof, 64);
+    R.part = NP;
+    NP += R.npp;
+    R.prob = PROB;
+    PROB += (long long)R.nblk * R.npp;
+    R.shadow = XS;
+    if (d.precision == PIMD_MIXED) XS += (long long)d.P * R.npad * dp;
+    maxn = std::max(maxn, q.n);
+    R.beta = q.beta; R.hbar = q.hbar; R.mass = q.mass; R.omega = q.omega; R.xi = q.xi;
+    R.amp = q.pair_amp; R.width = q.pair_amp > 0 ? q.pair_width : 1.0; R.dt = q.dt;
+    const double wp2 = (double)d.P / (q.beta * q.beta * q.hbar * q.hbar);
+    R.c = 0.5 * q.mass * wp2;
+    R.kappa = q.mass * wp2;
+    R.q = q.nhc_q > 0 ? q.nhc_q : 1.0 / (q.beta * wp2);
+    R.mp = q.bead_mass > 0 ? q.bead_mass : q.mass;
+    R.lnxi = q.xi > 0 ? std::log(q.xi) : -INFINITY;
+    R.mw2 = q.mass * q.omega * q.omega;
+    R.inv_s2 = q.pair_amp > 0 ? 1.0 / (q.pair_width * q.pair_width) : 0.0;
+    R.spw0 = (long long)pl.springwork.size();
+    for (int l0 = 0; l0 < q.n; l0 += kSpringBlock) pl.springwork.push_back(make_int4(r, l0, 0, 0));
+    R.spw1 = (long long)pl.springwork.size();
+    R.rw0 = R.spw0; R.rw1 = R.spw1;
+    R.pw0 = (long long)pl.pairwork.size();
+    if (q.pair_amp > 0)
+      for (int j = 0; j < d.P; ++j)
+        for (int i0 = 0; i0 < q.n; i0 += ipw) pl.pairwork.push_back(make_int4(r, j, i0, 0));
+    R.pw1 = (long long)pl.pairwork.size();
+    for (int rb = 0; rb < R.nblk; ++rb)
+      for (int cb = 0; cb <= rb; ++cb) pl.probwork.push_back(make_int4(r, rb, cb, 0));
+  }
+  d.G = G; d.NPtot = NP; d.PROBtot = PROB; d.XStot = XS; d.maxn = maxn;
+  d.nspringwg = (long long)pl.springwork.size();
+  d.npairwork = (long long)pl.pairwork.size();
+  d.nprobwork = (long long)pl.probwork.size();
+  d.nreducewg = d.nspringwg;
+  // segment sizes in bytes
+  size_t sz[S_COUNT];
+  sz[S_REPS] = sizeof(RepDev) * d.R;
+  sz[S_X] = sz[S_P] = sz[S_F] = sz[S_FPAIR] = 8ull * G;
+  sz[S_XS] = 4ull * XS;
+  sz[S_ETA] = sz[S_VETA] = 8ull * G * d.M;
+  sz[S_ENDS] = 8ull * 2 * d.D * NP;
+  sz[S_LINK] = sz[S_EINT] = sz[S_GF] = sz[S_GB] = 8ull * NP;
+  sz[S_ROWP] = sz[S_COLP] = 8ull * (d.D + 2) * PROB;
+  sz[S_SPRINGP] = 8ull * 4 * d.nspringwg;
+  sz[S_PAIRP] = 8ull * 2 * std::max<long long>(d.npairwork, 1);
+  sz[S_REDP] = 8ull * 2 * d.nreducewg;
+  sz[S_REC] = 8ull * kRec * d.R;
+  sz[S_TRACE] = 8ull * kRec * d.R * (size_t)d.cap;
+  sz[S_TRACECNT] = 8ull * d.R;
+  sz[S_DENS] = 8ull * d.R * (d.bins + 1);
+  sz[S_DENSN] = 8ull * d.R;
+  sz[S_SPRINGW] = sizeof(int4) * d.nspringwg;
+  sz[S_PAIRW] = sizeof(int4) * std::max<long long>(d.npairwork, 1);
+  sz[S_PROBW] = sizeof(int4) * d.nprobwork;
+  sz[S_DBG] = 8ull * std::max<long long>(2LL * (maxn + 2), std::min<long long>((long long)maxn * maxn, 1LL << 20));
+  size_t o = 0;
+  for (int s = 0; s < S_COUNT; ++s) {
+    pl.off[s] = o;
+    o += (size_t)round_up((long long)sz[s], 256);
+  }
+  pl.total = o;
+}
+
+}  // namespace
+
+struct pimd_ctx {
+  Plan pl;
+  DevPtrs w{};
+  char* ws = nullptr;
+  hipStream_t s = nullptr, s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool forces_valid = false;
+  bool evaluated = false;
+  long long step = 0;
+  bool has_pair = false;
+  bool profiling = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[K_COUNT] = {};
+  long long prof_n[K_COUNT] = {};
+};
+
+namespace {
+
+hipEvent_t take_event(pimd_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs `launch` on stream st, bracketed by events when profiling.
+template <class F>
+pimd_status timed(pimd_ctx* c, int kind, hipStream_t st, F&& launch) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profiling) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (!e0 || !e1) return fail(PIMD_ERR_DEVICE, "hipEventCreate failed");
+    HIPCHK(hipEventRecord(e0, st));
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return fail(PIMD_ERR_DEVICE, std::string("kernel launch (") + kKindNames[kind] + "): " + hipGetErrorString(e));
+  if (c->profiling) {
+    HIPCHK(hipEventRecord(e1, st));
+    c->prof.push_back({kind, {e0, e1}});
+    if (c->prof.size() > 4096) {  // fold finished records to bound the pool
+      HIPCHK(hipEventSynchronize(e1));
+      for (auto& pr : c->prof) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pr.second.first, pr.second.second));
+        c->prof_ms[pr.first] += ms;
+        c->prof_n[pr.first] += 1;
+        c->ev_pool.push_back(pr.second.first);
+        c->ev_pool.push_back(pr.second.second);
+      }
+      c->prof.clear();
+    }
+  }
+  return PIMD_OK;
+}
+
+#define RUN(kind, st, expr)                                      \
+  do {                                                           \
+    pimd_status r_ = timed(c, kind, st, [&]() { return (expr); }); \
+    if (r_ != PIMD_OK) return r_;                                \
+  } while (0)
+
+// One force evaluation of every replica at the current positions.
+pimd_status evaluate(pimd_ctx* c, bool est) {
+  const Dims& d = c->pl.d;
+  const DevPtrs& w = c->w;
+  RUN(K_SPRINGS, c->s, launch_springs(d, w, c->s));
+  const bool fork = c->has_pair && !c->profiling;
+  hipStream_t ps = fork ? c->s2 : c->s;
+  if (c->has_pair) {
+    if (fork) {
+      HIPCHK(hipEventRecord(c->ev_fork, c->s));
+      HIPCHK(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+    }
+    RUN(K_PAIR, ps, launch_pair(d, w, est, c->pl.jsplit, ps));
+    if (fork) HIPCHK(hipEventRecord(c->ev_join, c->s2));
+  }
+  RUN(K_RECURSION, c->s, launch_recursion(d, w, c->s));
+  RUN(K_PROBS, c->s, launch_probs(d, w, c->s));
+  RUN(K_REDUCE, c->s, launch_probs_reduce(d, w, c->s));
+  if (fork) HIPCHK(hipStreamWaitEvent(c->s, c->ev_join, 0));
+  return PIMD_OK;
+}
+
+pimd_status sample(pimd_ctx* c, bool record) {
+  const Dims& d = c->pl.d;
+  RUN(K_EST, c->s, launch_estimators(d, c->w, c->step, record, c->s));
+  if (record) RUN(K_DENS, c->s, launch_density(d, c->w, c->s));
+  return PIMD_OK;
+}
+
+pimd_status check_ctx_r(pimd_ctx* c, int32_t r) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  if (r < 0 || r >= c->pl.d.R) return fail(PIMD_ERR_INVALID, "replica index out of range");
+  return PIMD_OK;
+}
+
+hipMemcpyKind kind_in(pimd_mem m) { return m == PIMD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+hipMemcpyKind kind_out(pimd_mem m) { return m == PIMD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+}  // namespace
+
+extern "C" {
+
+int pimd_abi_version(void) { return PIMD_ABI_VERSION; }
+
+const char* pimd_last_error(void) { return g_err.c_str(); }
+
+pimd_status pimd_workspace_bytes(const pimd_config* cfg, size_t* bytes) {
+  pimd_status st = validate(cfg);
+  if (st != PIMD_OK) return st;
+  if (!bytes) return fail(PIMD_ERR_INVALID, "bytes is NULL");
+  Plan pl;
+  make_plan(cfg, pl);
+  *bytes = pl.total;
+  return PIMD_OK;
+}
+
+pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes, void* hip_stream, pimd_ctx** out) {
+  pimd_status st = validate(cfg);
+  if (st != PIMD_OK) return st;
+  if (!out) return fail(PIMD_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  pimd_ctx* c = new pimd_ctx();
+  make_plan(cfg, c->pl);
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u) || bytes < c->pl.total) {
+    size_t need = c->pl.total;
+    delete c;
+    return fail(PIMD_ERR_WORKSPACE, "workspace must be 256-byte aligned and at least " + std::to_string(need) + " bytes");
+  }
+  c->ws = (char*)d_workspace;
+  c->s = (hipStream_t)hip_stream;
+  const size_t* off = c->pl.off;
+  DevPtrs& w = c->w;
+  w.reps = (RepDev*)(c->ws + off[S_REPS]);
+  w.x = (double*)(c->ws + off[S_X]);
+  w.p = (double*)(c->ws + off[S_P]);
+  w.f = (double*)(c->ws + off[S_F]);
+  w.fpair = (double*)(c->ws + off[S_FPAIR]);
+  w.xs = (float*)(c->ws + off[S_XS]);
+  w.eta = (double*)(c->ws + off[S_ETA]);
+  w.veta = (double*)(c->ws + off[S_VETA]);
+  w.ends = (double*)(c->ws + off[S_ENDS]);
+  w.link = (double*)(c->ws + off[S_LINK]);
+  w.eint = (double*)(c->ws + off[S_EINT]);
+  w.gf = (double*)(c->ws + off[S_GF]);
+  w.gb = (double*)(c->ws + off[S_GB]);
+  w.rowpart = (double*)(c->ws + off[S_ROWP]);
+  w.colpart = (double*)(c->ws + off[S_COLP]);
+  w.springpart = (double*)(c->ws + off[S_SPRINGP]);
+  w.pairpart = (double*)(c->ws + off[S_PAIRP]);
+  w.reducepart = (double*)(c->ws + off[S_REDP]);
+  w.rec = (double*)(c->ws + off[S_REC]);
+  w.trace = (double*)(c->ws + off[S_TRACE]);
+  w.tracecount = (long long*)(c->ws + off[S_TRACECNT]);
+  w.dens = (unsigned long long*)(c->ws + off[S_DENS]);
+  w.denssamples = (long long*)(c->ws + off[S_DENSN]);
+  w.springwork = (int4*)(c->ws + off[S_SPRINGW]);
+  w.pairwork = (int4*)(c->ws + off[S_PAIRW]);
+  w.probwork = (int4*)(c->ws + off[S_PROBW]);
+  w.reducework = w.springwork;
+  w.dbg = (double*)(c->ws + off[S_DBG]);
+  for (auto& r : c->pl.reps) c->has_pair = c->has_pair || r.amp > 0;
+  auto cleanup = [&](pimd_status s2) {
+    if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    delete c;
+    return s2;
+  };
+  hipError_t e = hipMemsetAsync(c->ws, 0, c->pl.total, c->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(w.reps, c->pl.reps.data(), sizeof(RepDev) * c->pl.reps.size(), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess && !c->pl.springwork.empty())
+    e = hipMemcpyAsync(w.springwork, c->pl.springwork.data(), sizeof(int4) * c->pl.springwork.size(), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess && !c->pl.pairwork.empty())
+    e = hipMemcpyAsync(w.pairwork, c->pl.pairwork.data(), sizeof(int4) * c->pl.pairwork.size(), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess && !c->pl.probwork.empty())
+    e = hipMemcpyAsync(w.probwork, c->pl.probwork.data(), sizeof(int4) * c->pl.probwork.size(), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) return cleanup(fail(PIMD_ERR_DEVICE, std::string("pimd_create: ") + hipGetErrorString(e)));
+  *out = c;
+  return PIMD_OK;
+}
+
+pimd_status pimd_destroy(pimd_ctx* c) {
+  if (!c) return PIMD_OK;
+  (void)hipStreamSynchronize(c->s);
+  if (c->s2) (void)hipStreamSynchronize(c->s2);
+  for (auto& pr : c->prof) { (void)hipEventDestroy(pr.second.first); (void)hipEventDestroy(pr.second.second); }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->s2) (void)hipStreamDestroy(c->s2);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  delete c;
+  return PIMD_OK;
+}
+
+pimd_status pimd_set_state(pimd_ctx* c, int32_t r, const double* x, const double* p, const double* nhc, pimd_mem where) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!x) return fail(PIMD_ERR_INVALID, "x is NULL");
+  if (where != PIMD_HOST && where != PIMD_DEVICE) return fail(PIMD_ERR_INVALID, "bad memory kind");
+  const RepDev& R = c->pl.reps[r];
+  const Dims& d = c->pl.d;
+  const size_t nb = sizeof(double) * (size_t)R.ndof;
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpyAsync(c->w.x + R.dof, x, nb, kind_in(where), c->s));
+  if (p) HIPCHK(hipMemcpyAsync(c->w.p + R.dof, p, nb, kind_in(where), c->s));
+  else HIPCHK(hipMemsetAsync(c->w.p + R.dof, 0, nb, c->s));
+  for (int k = 0; k < d.M; ++k) {
+    if (nhc) {
+      HIPCHK(hipMemcpyAsync(c->w.eta + (long long)k * d.G + R.dof, nhc + (size_t)k * R.ndof, nb, kind_in(where), c->s));
+      HIPCHK(hipMemcpyAsync(c->w.veta + (long long)k * d.G + R.dof, nhc + (size_t)(d.M + k) * R.ndof, nb, kind_in(where), c->s));
+    } else {
+      HIPCHK(hipMemsetAsync(c->w.eta + (long long)k * d.G + R.dof, 0, nb, c->s));
+      HIPCHK(hipMemsetAsync(c->w.veta + (long long)k * d.G + R.dof, 0, nb, c->s));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c->s));
+  c->forces_valid = false;
+  return PIMD_OK;
+}
+
+pimd_status pimd_get_state(pimd_ctx* c, int32_t r, double* x, double* p, double* nhc, pimd_mem where) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (where != PIMD_HOST && where != PIMD_DEVICE) return fail(PIMD_ERR_INVALID, "bad memory kind");
+  const RepDev& R = c->pl.reps[r];
+  const Dims& d = c->pl.d;
+  const size_t nb = sizeof(double) * (size_t)R.ndof;
+  if (x) HIPCHK(hipMemcpyAsync(x, c->w.x + R.dof, nb, kind_out(where), c->s));
+  if (p) HIPCHK(hipMemcpyAsync(p, c->w.p + R.dof, nb, kind_out(where), c->s));
+  if (nhc)
+    for (int k = 0; k < d.M; ++k) {
+      HIPCHK(hipMemcpyAsync(nhc + (size_t)k * R.ndof, c->w.eta + (long long)k * d.G + R.dof, nb, kind_out(where), c->s));
+      HIPCHK(hipMemcpyAsync(nhc + (size_t)(d.M + k) * R.ndof, c->w.veta + (long long)k * d.G + R.dof, nb, kind_out(where), c->s));
+    }
+  HIPCHK(hipStreamSynchronize(c->s));
+  return PIMD_OK;
+}
+
+pimd_status pimd_compute_forces(pimd_ctx* c) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  pimd_status st = evaluate(c, true);
+  if (st != PIMD_OK) return st;
+  RUN(K_INT2, c->s, launch_integrate_second(c->pl.d, c->w, false, c->s));
+  st = sample(c, false);
+  if (st != PIMD_OK) return st;
+  c->forces_valid = true;
+  c->evaluated = true;
+  return PIMD_OK;
+}
+
+pimd_status pimd_get_forces(pimd_ctx* c, int32_t r, double* f, pimd_mem where) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!f) return fail(PIMD_ERR_INVALID, "f is NULL");
+  if (!c->forces_valid) return fail(PIMD_ERR_STATE, "no force evaluation since the last set_state");
+  const RepDev& R = c->pl.reps[r];
+  HIPCHK(hipMemcpyAsync(f, c->w.f + R.dof, sizeof(double) * (size_t)R.ndof, kind_out(where), c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return PIMD_OK;
+}
+
+pimd_status pimd_step(pimd_ctx* c, int64_t n_steps, int32_t sample_every) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  if (n_steps < 0 || sample_every < 0) return fail(PIMD_ERR_INVALID, "n_steps and sample_every must be >= 0");
+  const Dims& d = c->pl.d;
+  pimd_status st;
+  if (!c->forces_valid && n_steps > 0) {
+    if ((st = evaluate(c, false)) != PIMD_OK) return st;
+    RUN(K_INT2, c->s, launch_integrate_second(d, c->w, false, c->s));
+    c->forces_valid = true;
+  }
+  for (int64_t it = 0; it < n_steps; ++it) {
+    const bool smp = sample_every > 0 && ((c->step + 1) % sample_every == 0);
+    RUN(K_INT1, c->s, launch_integrate_first(d, c->w, c->s));
+    if ((st = evaluate(c, smp)) != PIMD_OK) return st;
+    RUN(K_INT2, c->s, launch_integrate_second(d, c->w, true, c->s));
+    c->step += 1;
+    if (smp) {
+      if ((st = sample(c, true)) != PIMD_OK) return st;
+      c->evaluated = true;
+    }
+  }
+  return PIMD_OK;
+}
+
+static void rec_to_struct(const double* o, pimd_estimates* e) {
+  e->v_exch = o[kVExch]; e->u_trap = o[kUTrap]; e->u_pair = o[kUPair]; e->spring_expect = o[kSpring];
+  e->virial = o[kVirial]; e->e_prim = o[kEPrim]; e->e_vir = o[kEVir]; e->kinetic = o[kKinetic];
+  e->nhc_energy = o[kNhcE]; e->h_conserved = o[kHCons]; e->step = (int64_t)o[kStep];
+}
+
+pimd_status pimd_energies(pimd_ctx* c, int32_t r, pimd_estimates* out) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!out) return fail(PIMD_ERR_INVALID, "out is NULL");
+  double o[kRec];
+  HIPCHK(hipMemcpyAsync(o, c->w.rec + (long long)kRec * r, sizeof(o), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (o[kValid] != 1.0) return fail(PIMD_ERR_STATE, "no sampled evaluation yet");
+  rec_to_struct(o, out);
+  for (int k = 0; k < kStep; ++k)
+    if (!std::isfinite(o[k])) return fail(PIMD_ERR_NONFINITE, "replica " + std::to_string(r) + ": non-finite estimator");
+  return PIMD_OK;
+}
+
+pimd_status pimd_trace(pimd_ctx* c, int32_t r, pimd_estimates* out, int64_t max_samples, int64_t* n_samples) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!n_samples || max_samples < 0 || (max_samples > 0 && !out)) return fail(PIMD_ERR_INVALID, "bad output arguments");
+  const Dims& d = c->pl.d;
+  long long cnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, c->w.tracecount + r, sizeof(cnt), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  long long avail = std::min<long long>(cnt, d.cap);
+  long long take = std::min<long long>(avail, max_samples);
+  std::vector<double> buf((size_t)d.cap * kRec);
+  if (take > 0) {
+    HIPCHK(hipMemcpyAsync(buf.data(), c->w.trace + (long long)r * d.cap * kRec, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    for (long long k = 0; k < take; ++k) {
+      long long idx = (cnt - take + k) % d.cap;
+      rec_to_struct(&buf[(size_t)idx * kRec], &out[k]);
+    }
+  }
+  *n_samples = take;
+  return PIMD_OK;
+}
+
+pimd_status pimd_density(pimd_ctx* c, int32_t r, uint64_t* counts, int64_t* n_samples) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!counts || !n_samples) return fail(PIMD_ERR_INVALID, "NULL output");
+  const Dims& d = c->pl.d;
+  long long ns = 0;
+  HIPCHK(hipMemcpyAsync(counts, c->w.dens + (long long)r * (d.bins + 1), 8ull * (d.bins + 1), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipMemcpyAsync(&ns, c->w.denssamples + r, sizeof(ns), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  *n_samples = ns;
+  return PIMD_OK;
+}
+
+pimd_status pimd_reset_accumulators(pimd_ctx* c) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  const size_t* off = c->pl.off;
+  const Dims& d = c->pl.d;
+  HIPCHK(hipMemsetAsync(c->ws + off[S_TRACECNT], 0, 8ull * d.R, c->s));
+  HIPCHK(hipMemsetAsync(c->ws + off[S_DENS], 0, 8ull * d.R * (d.bins + 1), c->s));
+  HIPCHK(hipMemsetAsync(c->ws + off[S_DENSN], 0, 8ull * d.R, c->s));
+  return PIMD_OK;
+}
+
+pimd_status pimd_debug_potentials(pimd_ctx* c, int32_t r, double* X, double* Y) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!X || !Y) return fail(PIMD_ERR_INVALID, "NULL output");
+  if (!c->forces_valid) return fail(PIMD_ERR_STATE, "no force evaluation since the last set_state");
+  const int N = c->pl.reps[r].n;
+  double* dX = c->w.dbg;
+  double* dY = c->w.dbg + (N + 2);
+  HIPCHK(launch_debug_potentials(c->pl.d, c->w, r, dX, dY, c->s));
+  HIPCHK(hipMemcpyAsync(X, dX, sizeof(double) * (N + 1), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipMemcpyAsync(Y, dY, sizeof(double) * (N + 2), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return PIMD_OK;
+}
+
+pimd_status pimd_debug_probs(pimd_ctx* c, int32_t r, double* G) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!G) return fail(PIMD_ERR_INVALID, "NULL output");
+  if (!c->forces_valid) return fail(PIMD_ERR_STATE, "no force evaluation since the last set_state");
+  const long long N = c->pl.reps[r].n;
+  const long long cap = std::max<long long>(2LL * (c->pl.d.maxn + 2), std::min<long long>((long long)c->pl.d.maxn * c->pl.d.maxn, 1LL << 20));
+  const long long rows = std::max<long long>(1, cap / N);
+  for (long long r0 = 0; r0 < N; r0 += rows) {
+    const long long nr = std::min(rows, N - r0);
+    HIPCHK(launch_debug_probs(c->pl.d, c->w, r, (int)N, (int)r0, (int)nr, c->w.dbg, c->s));
+    HIPCHK(hipMemcpyAsync(G + r0 * N, c->w.dbg, sizeof(double) * nr * N, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+  }
+  return PIMD_OK;
+}
+
+pimd_status pimd_profile(pimd_ctx* c, int enable) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  HIPCHK(hipStreamSynchronize(c->s));
+  for (auto& pr : c->prof) { c->ev_pool.push_back(pr.second.first); c->ev_pool.push_back(pr.second.second); }
+  c->prof.clear();
+  for (int k = 0; k < K_COUNT; ++k) { c->prof_ms[k] = 0.0; c->prof_n[k] = 0; }
+  c->profiling = enable != 0;
+  return PIMD_OK;
+}
+
+pimd_status pimd_kernel_times(pimd_ctx* c, double* ms, int64_t* launches, int32_t max_kinds, int32_t* n_kinds) {
+  if (!c || !n_kinds || max_kinds < 0 || (max_kinds > 0 && (!ms || !launches))) return fail(PIMD_ERR_INVALID, "bad arguments");
+  HIPCHK(hipStreamSynchronize(c->s));
+  for (auto& pr : c->prof) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, pr.second.first, pr.second.second));
+    c->prof_ms[pr.first] += t;
+    c->prof_n[pr.first] += 1;
+    c->ev_pool.push_back(pr.second.first);
+    c->ev_pool.push_back(pr.second.second);
+  }
+  c->prof.clear();
+  for (int k = 0; k < K_COUNT && k < max_kinds; ++k) { ms[k] = c->prof_ms[k]; launches[k] = c->prof_n[k]; }
+  *n_kinds = K_COUNT;
+  return PIMD_OK;
+}
+
+const char* pimd_kernel_name(int32_t kind) {
+  if (kind < 0 || kind >= K_COUNT) return "";
+  return kKindNames[kind];
+}
+
+pimd_status pimd_synchronize(pimd_ctx* c) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  HIPCHK(hipStreamSynchronize(c->s));
+  return PIMD_OK;
+}
+
+}  // extern "C"

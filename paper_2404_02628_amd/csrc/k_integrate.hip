@@ -1,0 +1,282 @@
+// k_integrate.hip -- velocity Verlet with massive Nose-Hoover chains, estimators, density.
+//
+// The paper samples exp(-beta (V_xi + U/P)) by molecular dynamics with massive Nose-Hoover
+// chains (Sec. IV.A).  Every Cartesian bead coordinate has its own chain of length M with
+// masses Q and target k_B T = 1/beta.  A step is
+//   NHC(dt/2); p += F dt/2; x += p dt/m'; F = force(x); p += F dt/2; NHC(dt/2),
+// where NHC(tau) is the Suzuki-Yoshida factorised chain propagator of Martyna, Tuckerman,
+// Tobias and Klein (Mol. Phys. 87, 1117 (1996)) with one multiple-time-step cycle.
+// All of it is FP64 and elementwise over degrees of freedom (HBM-bound).
+#include "pimd_internal.h"
+#include "device_util.h"
+
+namespace pimd {
+
+struct SyW { double w[5]; int n; };
+
+__device__ inline void nhc_propagate(double& p, double mp, double* eta, double* v, int M, double Q, double kT,
+                                     double tau, const SyW& sy) {
+  for (int iw = 0; iw < sy.n; ++iw) {
+    const double h = sy.w[iw] * tau;
+    {
+      double Gm = (M == 1) ? (p * p / mp - kT) / Q : (Q * v[M - 2] * v[M - 2] - kT) / Q;
+      v[M - 1] += 0.5 * h * Gm;
+    }
+    for (int k = M - 2; k >= 0; --k) {
+      double sc = exp(-0.25 * h * v[k + 1]);
+      double Gk = (k == 0) ? (p * p / mp - kT) / Q : (Q * v[k - 1] * v[k - 1] - kT) / Q;
+      v[k] = (v[k] * sc + 0.5 * h * Gk) * sc;
+    }
+    p *= exp(-h * v[0]);
+    for (int k = 0; k < M; ++k) eta[k] += h * v[k];
+    for (int k = 0; k <= M - 2; ++k) {
+      double sc = exp(-0.25 * h * v[k + 1]);
+      double Gk = (k == 0) ? (p * p / mp - kT) / Q : (Q * v[k - 1] * v[k - 1] - kT) / Q;
+      v[k] = (v[k] * sc + 0.5 * h * Gk) * sc;
+    }
+    {
+      double Gm = (M == 1) ? (p * p / mp - kT) / Q : (Q * v[M - 2] * v[M - 2] - kT) / Q;
+      v[M - 1] += 0.5 * h * Gm;
+    }
+  }
+}
+
+template <int M>
+__device__ inline void nhc_half(double& p, const RepDev& R, double* eta, double* veta, long long gi, long long G,
+                                const SyW& sy) {
+  if (M == 0) return;
+  double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
+#pragma unroll
+  for (int k = 0; k < M; ++k) { e[k] = eta[k * G + gi]; v[k] = veta[k * G + gi]; }
+  nhc_propagate(p, R.mp, e, v, M, R.q, 1.0 / R.beta, 0.5 * R.dt, sy);
+#pragma unroll
+  for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
+}
+
+// Thread -> degree of freedom; the spring work list doubles as the dof work list
+// (workgroup g covers dofs [l0*D*P, ...) of its replica in chunks of 256 particles).
+template <int M>
+__global__ __launch_bounds__(256) void k_integrate_first(const RepDev* __restrict__ reps,
+                                                         const int4* __restrict__ work, double* __restrict__ x,
+                                                         double* __restrict__ p, const double* __restrict__ f,
+                                                         double* __restrict__ eta, double* __restrict__ veta,
+                                                         long long G, int DP, SyW sy) {
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const long long nd = R.ndof;
+  // each workgroup of the spring list owns 256 particles; as a dof list it owns DP*256 dofs
+  const long long base = (long long)wk.y * DP;
+  for (int k = 0; k < DP; ++k) {
+    const long long li = base + (long long)k * 256 + threadIdx.x;
+    if (li >= nd) break;
+    const long long gi = R.dof + li;
+    double pv = p[gi];
+    nhc_half<M>(pv, R, eta, veta, gi, G, sy);
+    pv += 0.5 * R.dt * f[gi];
+    x[gi] += R.dt * pv / R.mp;
+    p[gi] = pv;
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_integrate_second(const RepDev* __restrict__ reps,
+                                                          const int4* __restrict__ work, double* __restrict__ p,
+                                                          double* __restrict__ f, const double* __restrict__ fpair,
+                                                          double* __restrict__ eta, double* __restrict__ veta,
+                                                          long long G, int DP, SyW sy, int kick) {
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const long long nd = R.ndof;
+  const long long base = (long long)wk.y * DP;
+  const bool pair = R.amp > 0.0;
+  for (int k = 0; k < DP; ++k) {
+    const long long li = base + (long long)k * 256 + threadIdx.x;
+    if (li >= nd) break;
+    const long long gi = R.dof + li;
+    double fv = f[gi];
+    if (pair) fv += fpair[gi];
+    f[gi] = fv;
+    if (kick) {
+      double pv = p[gi] + 0.5 * R.dt * fv;
+      nhc_half<M>(pv, R, eta, veta, gi, G, sy);
+      p[gi] = pv;
+    }
+  }
+}
+
+// One workgroup per replica: kinetic and thermostat energies over all dofs plus the
+// partial sums left by the spring, pair and probability kernels, in a fixed order.
+__global__ __launch_bounds__(256) void k_estimators(const RepDev* __restrict__ reps, const double* __restrict__ p,
+                                                    const double* __restrict__ eta, const double* __restrict__ veta,
+                                                    const double* __restrict__ gf,
+                                                    const double* __restrict__ springpart,
+                                                    const double* __restrict__ pairpart,
+                                                    const double* __restrict__ reducepart, double* __restrict__ rec,
+                                                    double* __restrict__ trace, long long* __restrict__ tracecount,
+                                                    long long G, int M, int D, int P, int cap, long long step,
+                                                    int record) {
+  __shared__ double lds[2 * 4];
+  const int r = blockIdx.x;
+  const RepDev& R = reps[r];
+  double acc[2] = {0.0, 0.0};
+  const double kT = 1.0 / R.beta;
+  for (long long li = threadIdx.x; li < R.ndof; li += blockDim.x) {
+    const long long gi = R.dof + li;
+    const double pv = p[gi];
+    acc[0] += 0.5 * pv * pv / R.mp;
+    for (int k = 0; k < M; ++k) {
+      const double v = veta[k * G + gi];
+      acc[1] += 0.5 * R.q * v * v + kT * eta[k * G + gi];
+    }
+  }
+  block_sum<2>(acc, lds);
+  if (threadIdx.x != 0) return;
+  double eint = 0.0, lk = 0.0, ut = 0.0;
+  for (long long g = R.spw0; g < R.spw1; ++g) {
+    eint += springpart[4 * g + 0];
+    lk += springpart[4 * g + 1];
+    ut += springpart[4 * g + 2];
+  }
+  double up = 0.0, wp = 0.0;
+  if (R.amp > 0.0) {
+    for (long long g = R.pw0; g < R.pw1; ++g) {
+      up += pairpart[2 * g + 0];
+      wp += pairpart[2 * g + 1];
+    }
+  }
+  double sx = 0.0;
+  for (long long g = R.rw0; g < R.rw1; ++g) sx += reducepart[2 * g + 0];
+  const int N = R.n;
+  const double S = eint + sx;
+  const double V = eint + lk - gf[R.part + N] / R.beta;
+  const double U = ut + up;
+  double* o = rec + (long long)kRec * r;
+  o[kVExch] = V;
+  o[kUTrap] = ut;
+  o[kUPair] = up;
+  o[kSpring] = S;
+  o[kVirial] = 2.0 * ut + wp;
+  o[kEPrim] = (double)D * N * P / (2.0 * R.beta) - S + U / (double)P;
+  o[kEVir] = (2.0 * ut + wp) / (double)P;
+  o[kKinetic] = acc[0];
+  o[kNhcE] = acc[1];
+  o[kHCons] = acc[0] + V + U / (double)P + acc[1];
+  o[kStep] = (double)step;
+  o[kEintSum] = eint;
+  o[kLinkSum] = lk;
+  o[kPairW] = wp;
+  o[kValid] = 1.0;
+  o[kRecPad] = 0.0;
+  if (record && cap > 0) {
+    const long long c = tracecount[r];
+    double* t = trace + ((long long)r * cap + (c % cap)) * kRec;
+    for (int k = 0; k < kRec; ++k) t[k] = o[k];
+    tracecount[r] = c + 1;
+  }
+}
+
+// Radial histogram of every bead of every replica (one workgroup per spring work item,
+// i.e. 256 particles, all slices).  Integer counts are exact, so atomics are deterministic.
+template <int D>
+__global__ __launch_bounds__(256) void k_density(const RepDev* __restrict__ reps, const int4* __restrict__ work,
+                                                 const double* __restrict__ x, unsigned long long* __restrict__ dens,
+                                                 long long* __restrict__ nsamp, int P, int bins, double rmax) {
+  extern __shared__ unsigned int hist[];
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const int N = R.n;
+  for (int b = threadIdx.x; b <= bins; b += blockDim.x) hist[b] = 0u;
+  __syncthreads();
+  const int l = wk.y + threadIdx.x;
+  if (l < N) {
+    const double* xr = x + R.dof;
+    for (int j = 0; j < P; ++j) {
+      // the bin is an integer decided by floating point: evaluate |r| exactly as
+      // sum of squares in component order (no contraction), then (|r|/rmax)*bins
+      double r2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double v = xr[((long long)a * P + j) * N + l];
+        r2 = __dadd_rn(r2, __dmul_rn(v, v));
+      }
+      double rr = __dsqrt_rn(r2);
+      // NaN and |r| >= rmax go to the overflow bin
+      int b = (rr < rmax) ? (int)__dmul_rn(__ddiv_rn(rr, rmax), (double)bins) : bins;
+      if (b < 0) b = 0;
+      if (b > bins) b = bins;
+      atomicAdd(&hist[b], 1u);
+    }
+  }
+  __syncthreads();
+  unsigned long long* dr = dens + (long long)wk.x * (bins + 1);
+  for (int b = threadIdx.x; b <= bins; b += blockDim.x)
+    if (hist[b]) atomicAdd(&dr[b], (unsigned long long)hist[b]);
+  if (threadIdx.x == 0 && blockIdx.x == R.spw0) nsamp[wk.x] += 1;
+}
+
+static SyW sy_weights(int order) {
+  SyW s{};
+  if (order == 1) { s.w[0] = 1.0; s.n = 1; }
+  else if (order == 3) {
+    double a = 1.0 / (2.0 - cbrt(2.0));
+    s.w[0] = a; s.w[1] = 1.0 - 2.0 * a; s.w[2] = a; s.n = 3;
+  } else {
+    double a = 1.0 / (4.0 - pow(4.0, 1.0 / 3.0));
+    s.w[0] = a; s.w[1] = a; s.w[2] = 1.0 - 4.0 * a; s.w[3] = a; s.w[4] = a; s.n = 5;
+  }
+  return s;
+}
+
+hipError_t launch_integrate_first(const Dims& d, const DevPtrs& w, hipStream_t s) {
+  if (d.nspringwg == 0) return hipSuccess;
+  dim3 grid((unsigned)d.nspringwg), block(256);
+  const SyW sy = sy_weights(d.sy_order);
+  const int DP = d.D * d.P;
+#define L(MM) hipLaunchKernelGGL(k_integrate_first<MM>, grid, block, 0, s, w.reps, w.springwork, w.x, w.p, w.f, \
+                                 w.eta, w.veta, d.G, DP, sy)
+  switch (d.M) {
+    case 0: L(0); break; case 1: L(1); break; case 2: L(2); break; case 3: L(3); break;
+    case 4: L(4); break; case 5: L(5); break; case 6: L(6); break; case 7: L(7); break; case 8: L(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef L
+  return hipGetLastError();
+}
+
+hipError_t launch_integrate_second(const Dims& d, const DevPtrs& w, bool kick, hipStream_t s) {
+  if (d.nspringwg == 0) return hipSuccess;
+  dim3 grid((unsigned)d.nspringwg), block(256);
+  const SyW sy = sy_weights(d.sy_order);
+  const int DP = d.D * d.P;
+#define L(MM) hipLaunchKernelGGL(k_integrate_second<MM>, grid, block, 0, s, w.reps, w.springwork, w.p, w.f, \
+                                 w.fpair, w.eta, w.veta, d.G, DP, sy, kick ? 1 : 0)
+  switch (d.M) {
+    case 0: L(0); break; case 1: L(1); break; case 2: L(2); break; case 3: L(3); break;
+    case 4: L(4); break; case 5: L(5); break; case 6: L(6); break; case 7: L(7); break; case 8: L(8); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef L
+  return hipGetLastError();
+}
+
+hipError_t launch_estimators(const Dims& d, const DevPtrs& w, long long step, bool record, hipStream_t s) {
+  hipLaunchKernelGGL(k_estimators, dim3(d.R), dim3(256), 0, s, w.reps, w.p, w.eta, w.veta, w.gf, w.springpart,
+                     w.pairpart, w.reducepart, w.rec, w.trace, w.tracecount, d.G, d.M, d.D, d.P, d.cap, step,
+                     record ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_density(const Dims& d, const DevPtrs& w, hipStream_t s) {
+  if (d.nspringwg == 0) return hipSuccess;
+  dim3 grid((unsigned)d.nspringwg), block(256);
+  size_t sh = sizeof(unsigned int) * (size_t)(d.bins + 1);
+  switch (d.D) {
+    case 1: hipLaunchKernelGGL(k_density<1>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax); break;
+    case 2: hipLaunchKernelGGL(k_density<2>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax); break;
+    case 3: hipLaunchKernelGGL(k_density<3>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pimd

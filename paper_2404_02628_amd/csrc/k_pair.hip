@@ -1,0 +1,211 @@
+// k_pair.hip -- all-pairs Gaussian interaction of every imaginary-time slice.
+//
+// U = sum_j V(slice j) (Eq. 5) with V = sum_{l<l'} A exp(-|r_l - r_l'|^2 / s^2) (Eq. 20, each
+// unordered pair once).  The sampled weight carries U/P (Eq. 4), so the force on bead (l, j) is
+//   F = (2A / (P s^2)) sum_{l'} exp(-|r_l - r_l'|^2/s^2) (r_l - r_l').
+// Each lane owns one particle i of one slice and sweeps the partner index j, which is the
+// same for the whole wavefront, so partner coordinates are wave-uniform loads.  Ordered pairs
+// are evaluated (i sees every j), which needs no write conflicts; the i = j term contributes
+// zero force and is masked out of the energies.
+//
+// Mixed precision: coordinates come from the FP32 shadow, pre-scaled by sqrt(log2 e)/s, so a
+// term is exp2(-|dr|^2) (one v_exp_f32); FP32 sums run over runs of kFold partners and are then
+// folded into FP64 accumulators.  FP64 mode reads the FP64 positions and uses exp().
+//
+// Estimator sums (only when requested): sum over ordered pairs of u and of u |dr|^2, giving
+// U_pair and the pair part of the virial W = sum_pairs u (1 - r^2/s^2).
+#include "pimd_internal.h"
+#include "device_util.h"
+
+namespace pimd {
+
+constexpr int kFold = 128;
+
+template <int D>
+struct Vec { float v[D == 3 ? 4 : D]; };
+
+// JS waves share one 64-particle tile, each sweeping 1/JS of the partners.
+template <int D, bool EST, int JS>
+__global__ __launch_bounds__(256) void k_pair_f32(const RepDev* __restrict__ reps, const int4* __restrict__ work,
+                                                  const float* __restrict__ xs, double* __restrict__ fpair,
+                                                  double* __restrict__ pairpart, int P) {
+  constexpr int DP = D == 3 ? 4 : D;
+  constexpr int IT = 4 / JS;          // 64-particle tiles per workgroup
+  __shared__ double red[4][D + 2][64];
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const int N = R.n, slice = wk.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int itile = wave / JS, jpart = wave % JS;
+  const int i = wk.z + itile * 64 + lane;
+  const float* xsl = xs + R.shadow + (long long)slice * R.npad * DP;
+  float xi[D];
+  const int ii = i < N ? i : N - 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) xi[a] = xsl[(long long)ii * DP + a];
+  const int jchunk = (N + JS - 1) / JS;
+  const int j0 = jpart * jchunk;
+  const int j1 = min(N, j0 + jchunk);
+  double F[D], U = 0.0, W = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) F[a] = 0.0;
+  for (int jb = j0; jb < j1; jb += kFold) {
+    const int je = min(j1, jb + kFold);
+    float f[D], u32 = 0.f, w32 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) f[a] = 0.f;
+#pragma unroll 4
+    for (int j = jb; j < je; ++j) {
+      float d[D], r2 = 0.f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        d[a] = xi[a] - xsl[(long long)j * DP + a];
+        r2 = __builtin_fmaf(d[a], d[a], r2);
+      }
+      float u = __builtin_amdgcn_exp2f(-r2);
+#pragma unroll
+      for (int a = 0; a < D; ++a) f[a] = __builtin_fmaf(u, d[a], f[a]);
+      if (EST) {
+        float um = (j == i) ? 0.f : u;
+        u32 += um;
+        w32 = __builtin_fmaf(um, r2, w32);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[a] += (double)f[a];
+    if (EST) { U += (double)u32; W += (double)w32; }
+  }
+  if (i >= N) { U = 0.0; W = 0.0; }
+  if (JS > 1) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) red[wave][a][lane] = F[a];
+    __syncthreads();
+    if (jpart == 0) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < JS; ++q) s += red[wave + q][a][lane];
+        F[a] = s;
+      }
+    }
+    __syncthreads();
+  }
+  if (jpart == 0 && i < N) {
+    // F = (2A/(P s^2 k)) * sum u (r'_i - r'_j) with r' = k r, k = sqrt(log2 e)/s
+    const double k = sqrt(1.4426950408889634) / R.width;
+    const double scale = 2.0 * R.amp / ((double)P * R.width * R.width * k);
+    double* fr = fpair + R.dof;
+#pragma unroll
+    for (int a = 0; a < D; ++a) fr[((long long)a * P + slice) * N + i] = scale * F[a];
+  }
+  if (EST) {
+    double v[2] = {U, W};
+    block_sum<2>(v, &red[0][0][0]);
+    if (threadIdx.x == 0) {
+      // u r'^2 = u r^2 log2(e)/s^2  ->  r^2/s^2 = r'^2 / log2(e)
+      pairpart[2LL * blockIdx.x + 0] = 0.5 * R.amp * v[0];
+      pairpart[2LL * blockIdx.x + 1] = 0.5 * R.amp * (v[0] - v[1] / 1.4426950408889634);
+    }
+  }
+}
+
+template <int D, bool EST, int JS>
+__global__ __launch_bounds__(256) void k_pair_f64(const RepDev* __restrict__ reps, const int4* __restrict__ work,
+                                                  const double* __restrict__ x, double* __restrict__ fpair,
+                                                  double* __restrict__ pairpart, int P) {
+  constexpr int IT = 4 / JS;
+  __shared__ double red[4][D + 2][64];
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const int N = R.n, slice = wk.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int itile = wave / JS, jpart = wave % JS;
+  const int i = wk.z + itile * 64 + lane;
+  const double inv_s = 1.0 / R.width;
+  const double* xr = x + R.dof;
+  double xi[D];
+  const int ii = i < N ? i : N - 1;
+#pragma unroll
+  for (int a = 0; a < D; ++a) xi[a] = xr[((long long)a * P + slice) * N + ii] * inv_s;
+  const int jchunk = (N + JS - 1) / JS;
+  const int j0 = jpart * jchunk;
+  const int j1 = min(N, j0 + jchunk);
+  double F[D], U = 0.0, W = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) F[a] = 0.0;
+#pragma unroll 2
+  for (int j = j0; j < j1; ++j) {
+    double d[D], r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      d[a] = xi[a] - xr[((long long)a * P + slice) * N + j] * inv_s;
+      r2 = fma(d[a], d[a], r2);
+    }
+    double u = exp(-r2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[a] = fma(u, d[a], F[a]);
+    if (EST) {
+      double um = (j == i) ? 0.0 : u;
+      U += um;
+      W = fma(um, r2, W);
+    }
+  }
+  if (i >= N) { U = 0.0; W = 0.0; }
+  if (JS > 1) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) red[wave][a][lane] = F[a];
+    __syncthreads();
+    if (jpart == 0) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < JS; ++q) s += red[wave + q][a][lane];
+        F[a] = s;
+      }
+    }
+    __syncthreads();
+  }
+  if (jpart == 0 && i < N) {
+    // F = (2A/(P s^2)) sum u (r_i - r_j) = (2A/(P s)) sum u (r'_i - r'_j), r' = r/s
+    const double scale = 2.0 * R.amp / ((double)P * R.width);
+    double* fr = fpair + R.dof;
+#pragma unroll
+    for (int a = 0; a < D; ++a) fr[((long long)a * P + slice) * N + i] = scale * F[a];
+  }
+  if (EST) {
+    double v[2] = {U, W};
+    block_sum<2>(v, &red[0][0][0]);
+    if (threadIdx.x == 0) {
+      pairpart[2LL * blockIdx.x + 0] = 0.5 * R.amp * v[0];
+      pairpart[2LL * blockIdx.x + 1] = 0.5 * R.amp * (v[0] - v[1]);
+    }
+  }
+}
+
+template <int D, bool EST>
+static void launch_pair_js(const Dims& d, const DevPtrs& w, int js, hipStream_t s) {
+  dim3 grid((unsigned)d.npairwork), block(256);
+  if (d.precision == 1) {
+    if (js == 4) hipLaunchKernelGGL((k_pair_f32<D, EST, 4>), grid, block, 0, s, w.reps, w.pairwork, w.xs, w.fpair, w.pairpart, d.P);
+    else if (js == 2) hipLaunchKernelGGL((k_pair_f32<D, EST, 2>), grid, block, 0, s, w.reps, w.pairwork, w.xs, w.fpair, w.pairpart, d.P);
+    else hipLaunchKernelGGL((k_pair_f32<D, EST, 1>), grid, block, 0, s, w.reps, w.pairwork, w.xs, w.fpair, w.pairpart, d.P);
+  } else {
+    if (js == 4) hipLaunchKernelGGL((k_pair_f64<D, EST, 4>), grid, block, 0, s, w.reps, w.pairwork, w.x, w.fpair, w.pairpart, d.P);
+    else if (js == 2) hipLaunchKernelGGL((k_pair_f64<D, EST, 2>), grid, block, 0, s, w.reps, w.pairwork, w.x, w.fpair, w.pairpart, d.P);
+    else hipLaunchKernelGGL((k_pair_f64<D, EST, 1>), grid, block, 0, s, w.reps, w.pairwork, w.x, w.fpair, w.pairpart, d.P);
+  }
+}
+
+// jsplit: waves per 64-particle tile (1, 2 or 4); the work list was built for this value.
+hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool est, int jsplit, hipStream_t s) {
+  if (d.npairwork == 0) return hipSuccess;
+  switch (d.D) {
+    case 1: est ? launch_pair_js<1, true>(d, w, jsplit, s) : launch_pair_js<1, false>(d, w, jsplit, s); break;
+    case 2: est ? launch_pair_js<2, true>(d, w, jsplit, s) : launch_pair_js<2, false>(d, w, jsplit, s); break;
+    case 3: est ? launch_pair_js<3, true>(d, w, jsplit, s) : launch_pair_js<3, false>(d, w, jsplit, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pimd

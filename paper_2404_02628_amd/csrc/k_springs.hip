@@ -1,0 +1,109 @@
+// k_springs.hip -- ring-polymer springs and the harmonic trap (HBM-bound).
+//
+// For every particle l of every replica, one pass over its P beads:
+//   * interior spring forces  -m omega_P^2 (2 r^j - r^{j+1} - r^{j-1}),  j = 2..P-1   (Eq. 17)
+//   * trap forces             -(1/P) m omega^2 r^j on every bead                      (Eqs. 4, 19)
+//   * E_int^{(l)} = (1/2) m omega_P^2 sum_{j<P} |r^{j+1} - r^j|^2                       (Eq. 9)
+//   * link_l = (1/2) m omega_P^2 |r_l^P - r_{l+1}^1|^2 (the inter-ring term of Eq. 7), 0 for l = N
+//   * the end beads r_l^1, r_l^P used by the exchange recursion (Eqs. 6-16)
+//   * in mixed precision, the FP32 shadow of the positions for the pair kernel, stored
+//     slice-major [P][N][dp] and pre-scaled by sqrt(log2 e)/s so the pair kernel evaluates
+//     exp(-|r|^2/s^2) as one exp2.
+// End-bead exchange forces (Eqs. 15-16) are added later by the probability reduction.
+// Per-workgroup partial sums (E_int, links, trap energy) go to springpart in a fixed order.
+#include "pimd_internal.h"
+#include "device_util.h"
+
+namespace pimd {
+
+template <int D, bool SHADOW>
+__global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restrict__ reps,
+                                                          const int4* __restrict__ work,
+                                                          const double* __restrict__ x, double* __restrict__ f,
+                                                          double* __restrict__ ends, double* __restrict__ link,
+                                                          double* __restrict__ eint, float* __restrict__ xs,
+                                                          double* __restrict__ springpart, int P) {
+  __shared__ double lds[3 * (kSpringBlock / 64)];
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const int N = R.n;
+  const int l = wk.y + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};  // E_int, link, U_trap
+  if (l < N) {
+    const double* xr = x + R.dof;
+    double* fr = f + R.dof;
+    const double kap = R.kappa, trap = R.mw2 / (double)P;
+    double e_int = 0.0, lk = 0.0, ut = 0.0;
+    double* a_out = ends + 2LL * D * R.part;
+    double* b_out = a_out + (long long)D * R.npp;
+    const float kscale = (float)(R.amp > 0.0 ? sqrt(1.4426950408889634) / R.width : 1.0);
+    const int dp = shadow_dp(D);
+    float* xsr = xs + R.shadow;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double* xa = xr + (long long)a * P * N;
+      double* fa = fr + (long long)a * P * N;
+      double rm = xa[l];           // bead 1
+      double r0 = rm;
+      double rp = xa[(long long)N + l];  // bead 2 (exists since P >= 2)
+      a_out[(long long)a * R.npp + l] = r0;
+      fa[l] = -trap * r0;
+      ut += r0 * r0;
+      if (SHADOW) xsr[((long long)0 * R.npad + l) * dp + a] = (float)r0 * kscale;
+      double d = rp - r0;
+      e_int += d * d;
+      double rc = rp;
+      for (int j = 1; j < P - 1; ++j) {
+        double rn = xa[(long long)(j + 1) * N + l];
+        fa[(long long)j * N + l] = -kap * (2.0 * rc - rn - rm) - trap * rc;
+        ut += rc * rc;
+        if (SHADOW) xsr[((long long)j * R.npad + l) * dp + a] = (float)rc * kscale;
+        double dd = rn - rc;
+        e_int += dd * dd;
+        rm = rc;
+        rc = rn;
+      }
+      // rc is bead P
+      fa[(long long)(P - 1) * N + l] = -trap * rc;
+      ut += rc * rc;
+      if (SHADOW) xsr[((long long)(P - 1) * R.npad + l) * dp + a] = (float)rc * kscale;
+      b_out[(long long)a * R.npp + l] = rc;
+      if (l + 1 < N) {
+        double dl = rc - xa[l + 1];
+        lk += dl * dl;
+      }
+    }
+    e_int *= R.c;
+    lk *= R.c;
+    ut *= 0.5 * R.mw2;
+    eint[R.part + l] = e_int;
+    link[R.part + l] = lk;   // zero for the last particle
+    acc[0] = e_int; acc[1] = lk; acc[2] = ut;
+  }
+  block_sum<3>(acc, lds);
+  if (threadIdx.x == 0) {
+    double* sp = springpart + 4LL * blockIdx.x;
+    sp[0] = acc[0]; sp[1] = acc[1]; sp[2] = acc[2]; sp[3] = 0.0;
+  }
+}
+
+hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s) {
+  if (d.nspringwg == 0) return hipSuccess;
+  dim3 grid((unsigned)d.nspringwg), block(kSpringBlock);
+  const bool sh = d.precision == 1;
+#define L(DD, SH) hipLaunchKernelGGL((k_springs<DD, SH>), grid, block, 0, s, w.reps, w.springwork, w.x, w.f, \
+                                     w.ends, w.link, w.eint, w.xs, w.springpart, d.P)
+  switch (d.D * 2 + (sh ? 1 : 0)) {
+    case 2: L(1, false); break;
+    case 3: L(1, true); break;
+    case 4: L(2, false); break;
+    case 5: L(2, true); break;
+    case 6: L(3, false); break;
+    case 7: L(3, true); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef L
+  return hipGetLastError();
+}
+
+}  // namespace pimd

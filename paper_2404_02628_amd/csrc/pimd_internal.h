@@ -1,0 +1,98 @@
+// pimd_internal.h -- device data layout shared by the libpimd translation units.
+//
+// One context holds R independent replicas that share P (beads), d (dim) and the
+// precision mode.  All device arrays live in the caller's workspace; this header
+// fixes how that workspace is carved up and what each kernel reads and writes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pimd {
+
+constexpr int kTile = 64;          // rows/columns of one exchange tile (= wavefront size)
+constexpr int kMaxNhc = 8;         // longest thermostat chain
+constexpr int kRec = 16;           // doubles per energy record
+constexpr int kSpringBlock = 256;  // particles per spring-kernel workgroup
+
+// Energy record slots (per replica, and per trace sample).
+enum RecSlot {
+  kVExch = 0, kUTrap, kUPair, kSpring, kVirial, kEPrim, kEVir, kKinetic, kNhcE, kHCons, kStep,
+  kEintSum, kLinkSum, kPairW, kValid, kRecPad
+};
+
+// Per-replica constants and offsets, resident in device memory.
+struct RepDev {
+  int n;            // particles N
+  int npad;         // N rounded up to kTile
+  int npp;          // per-replica stride of particle arrays (npad + kTile, holds N+1 entries)
+  int nblk;         // ceil(N / kTile)
+  long long dof;    // offset of this replica's x, p, f, fpair block ([dim][P][N], contiguous)
+  long long ndof;   // dim * P * N
+  long long part;   // offset unit for particle arrays (sum of npp of earlier replicas)
+  long long prob;   // offset unit for probability partials (sum of nblk*npp of earlier replicas)
+  long long shadow; // offset of the FP32 shadow ([P][npad][dp] floats)
+  long long spw0, spw1;    // spring workgroups [spw0, spw1)
+  long long pw0, pw1;      // pair work items [pw0, pw1)
+  long long rw0, rw1;      // probability-reduce workgroups [rw0, rw1)
+  double beta, hbar, mass, omega, xi, amp, width, dt, q, mp;
+  double c;         // (1/2) m omega_P^2, omega_P = sqrt(P)/(beta hbar)
+  double kappa;     // m omega_P^2
+  double lnxi;      // log(xi), -inf for xi = 0
+  double mw2;       // m omega^2 (trap)
+  double inv_s2;    // 1/s^2 (0 if no pair term)
+};
+
+// Device pointers into the workspace (all replicas concatenated).
+struct DevPtrs {
+  RepDev* reps;
+  double* x; double* p; double* f; double* fpair;
+  float* xs;                   // FP32 shadow of x for the pair kernel, layout per replica [P][npad][dp]
+  double* eta; double* veta;   // [M][G]
+  double* ends;                // per replica: [2*dim][npp]  (a = first beads, then b = last beads)
+  double* link;                // [npp]: c |b_l - a_{l+1}|^2, 0 for the last particle
+  double* eint;                // [npp]: internal spring energy of each ring
+  double* gf; double* gb;      // [npp]: forward / backward normalised log-potentials, rows 0..N
+  double* rowpart; double* colpart;  // [(dim+2)][nblk][npp] per replica
+  double* springpart;          // [nspringwg][4]
+  double* pairpart;            // [npairwork][2]
+  double* reducepart;          // [nreducewg][2]
+  double* rec;                 // [R][kRec] last estimators
+  double* trace;               // [R][cap][kRec]
+  long long* tracecount;       // [R]
+  unsigned long long* dens;    // [R][bins+1]
+  long long* denssamples;      // [R]
+  int4* springwork;            // {rep, l0, 0, 0}
+  int4* pairwork;              // {rep, slice, i0, 0}
+  int4* probwork;              // {rep, rb, cb, 0}
+  int4* reducework;            // {rep, l0, 0, 0}
+  double* dbg;                 // debug scratch (N+2 doubles of the largest replica, x2)
+};
+
+struct Dims {
+  int R, P, D, M, precision, sy_order, bins, cap;
+  double rmax;
+  long long G;                 // total dof (padded)
+  long long NPtot;             // sum of npp
+  long long PROBtot;           // sum of nblk*npp
+  long long XStot;             // floats in the shadow
+  long long nspringwg, npairwork, nprobwork, nreducewg;
+  int maxn;
+};
+
+__host__ __device__ inline int shadow_dp(int D) { return D == 3 ? 4 : D; }
+
+// Launchers (one per translation unit).
+hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s);
+hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool estimators, int jsplit, hipStream_t s);
+hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s);
+hipError_t launch_probs(const Dims& d, const DevPtrs& w, hipStream_t s);
+hipError_t launch_probs_reduce(const Dims& d, const DevPtrs& w, hipStream_t s);
+hipError_t launch_integrate_first(const Dims& d, const DevPtrs& w, hipStream_t s);
+hipError_t launch_integrate_second(const Dims& d, const DevPtrs& w, bool kick, hipStream_t s);
+hipError_t launch_estimators(const Dims& d, const DevPtrs& w, long long step, bool record, hipStream_t s);
+hipError_t launch_density(const Dims& d, const DevPtrs& w, hipStream_t s);
+hipError_t launch_debug_potentials(const Dims& d, const DevPtrs& w, int r, double* X, double* Y, hipStream_t s);
+hipError_t launch_debug_probs(const Dims& d, const DevPtrs& w, int r, int n, int row0, int nrows, double* G,
+                              hipStream_t s);
+
+}  // namespace pimd

@@ -77,6 +77,23 @@ def initial_state(sysm: System, seed: int | None = None):
     return np.ascontiguousarray(x), np.ascontiguousarray(p)
 
 
+def thermal_rings(n: int, p: int, dim: int, beta: float, sigma: float, seed: int, mass: float = 1.0,
+                  hbar: float = 1.0) -> np.ndarray:
+    """Ring polymers with centroids N(0, sigma^2) and internal shapes drawn from the free-ring
+    Boltzmann weight exp(-(beta m P / (2 (beta hbar)^2)) sum_j |r^{j+1} - r^j|^2): the bead
+    statistics of an equilibrated run, so test configurations have realistic spring energies."""
+    rng = np.random.default_rng(seed)
+    lap = 2.0 * np.eye(p) - np.roll(np.eye(p), 1, axis=1) - np.roll(np.eye(p), -1, axis=1)
+    lam, vec = np.linalg.eigh(lap)                       # lam[0] = 0 is the centroid mode
+    stiff = beta * mass * p / (beta * hbar) ** 2         # beta * m omega_P^2
+    shape_map = vec[:, 1:] / np.sqrt(stiff * lam[1:])    # (p, p-1)
+    out = np.empty((dim, p, n))
+    for a in range(dim):
+        out[a] = shape_map @ rng.normal(size=(p - 1, n))
+        out[a] += rng.normal(0.0, sigma, size=n)[None, :]
+    return np.ascontiguousarray(out)
+
+
 def random_positions(n: int, p: int, dim: int, sigma: float, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.normal(0.0, sigma, size=(dim, p, n)))

@@ -1,0 +1,79 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/pimd.h declares, and validates configurations on the host (no GPU call)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pimd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:pimd_status|int|const char\*)\s+(pimd_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_02628_amd import pimd
+    if not os.path.exists(pimd.LIB_PATH):
+        from paper_2404_02628_amd.build import build
+        build()
+    return pimd
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    raw = C.CDLL(lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+    assert set(names) == set(lib.EXPORTED)
+    assert lib.pimd_abi_version() == 1
+
+
+def _cfg(lib, **over):
+    reps = (lib.pimd_replica * 2)()
+    reps[0] = lib.pimd_replica(100, 0, 3.0, 1.0, 1.0, 1.0, 1.0, 2.0, 0.5, 0.01, 0.0, 0.0)
+    reps[1] = lib.pimd_replica(37, 0, 2.0, 1.0, 1.0, 1.0, 0.4, 0.0, 1.0, 0.01, 0.0, 0.0)
+    rep_over = over.pop("rep", {})
+    for k, v in rep_over.items():
+        setattr(reps[1], k, v)
+    kw = dict(n_replicas=2, p=12, dim=2, precision=1, nhc_len=4, sy_order=3, density_bins=50,
+              trace_capacity=10, density_rmax=5.0)
+    kw.update(over)
+    cfg = lib.pimd_config(kw["n_replicas"], kw["p"], kw["dim"], kw["precision"], kw["nhc_len"], kw["sy_order"],
+                          kw["density_bins"], kw["trace_capacity"], kw["density_rmax"], reps)
+    return cfg, reps
+
+
+def test_workspace_size_is_positive_and_monotone(lib):
+    cfg, _keep = _cfg(lib)
+    b1 = lib.pimd_workspace_bytes(cfg)
+    cfg2, _keep2 = _cfg(lib, rep={"n": 500})
+    b2 = lib.pimd_workspace_bytes(cfg2)
+    assert 0 < b1 < b2 and b1 % 256 == 0
+
+
+@pytest.mark.parametrize("over", [
+    {"p": 1}, {"dim": 0}, {"dim": 4}, {"precision": 7}, {"nhc_len": 9}, {"sy_order": 2},
+    {"density_bins": 0}, {"density_rmax": 0.0}, {"trace_capacity": -1}, {"n_replicas": 0},
+    {"rep": {"n": 0}}, {"rep": {"xi": -0.1}}, {"rep": {"xi": 1.5}}, {"rep": {"beta": 0.0}},
+    {"rep": {"pair_amp": -1.0}}, {"rep": {"pair_amp": 1.0, "pair_width": 0.0}}, {"rep": {"dt": 0.0}},
+    {"rep": {"reserved": 3}}, {"rep": {"mass": -1.0}},
+])
+def test_invalid_configs_are_rejected(lib, over):
+    cfg, _keep = _cfg(lib, **over)
+    with pytest.raises(lib.PimdError) as ei:
+        lib.pimd_workspace_bytes(cfg)
+    assert ei.value.code == lib.PIMD_ERR_INVALID
+    assert len(lib.pimd_last_error()) > 0
+
+
+def test_create_rejects_missing_workspace_without_touching_the_gpu(lib):
+    cfg, _keep = _cfg(lib)
+    with pytest.raises(lib.PimdError) as ei:
+        lib.pimd_create(cfg, 0, 0, 0)
+    assert ei.value.code == lib.PIMD_ERR_WORKSPACE
