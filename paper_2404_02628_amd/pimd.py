@@ -65,6 +65,10 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libpimd.so not found at {path}; build it with "
                            f"`python -m paper_2404_02628_amd.build` (hipcc, gfx950)")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7 and owns the device
+    # memory and stream handles this library is given, so it must be loaded first; libpimd's
+    # dependency on libamdhip64.so.7 then resolves to that same runtime.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     sig = {
         "pimd_abi_version": (C.c_int, []),

@@ -21,6 +21,7 @@ def lib():
     if not os.path.exists(pimd.LIB_PATH):
         from paper_2404_02628_amd.build import build
         build()
+    pimd.load()
     return pimd
 
 
