@@ -13,7 +13,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pimd_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PIMD_ORACLE_LIB points the wrapper at another build of the same source (used by the
+# mutation test, which compiles deliberately broken copies into a temporary directory).
+_LIB = os.environ.get("PIMD_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 
 
 def lib_path() -> str:

@@ -1,0 +1,52 @@
+"""The oracle's pins catch plausible mistakes: each mutation below is planted in a temporary
+copy of oracle/pimd_oracle.c (CPU only), compiled, and the pin suite must fail on it."""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTATIONS = {
+    "drop 1/l in Eq. 12": ("double lw = log_xi_pow(s->xi, l - lp) - log((double)l);",
+                           "double lw = log_xi_pow(s->xi, l - lp);"),
+    "transposed Pr in Eq. 15": ("double g_in = G[(size_t)(lp - 1) * N + (l - 1)];",
+                                "double g_in = G[(size_t)(l - 1) * N + (lp - 1)];"),
+    "local index in Eq. 11": ("- log((double)l) - (s->beta * e + Y[l + 1]);",
+                              "- log((double)(l - u + 1)) - (s->beta * e + Y[l + 1]);"),
+    "sign in Eq. 10": ("+ c * sqdist_beads(s, x, P, u, 1, u + 1)", "- c * sqdist_beads(s, x, P, u, 1, u + 1)"),
+    "xi power in Eq. 6": ("t[k - 1] = log_xi_pow(s->xi, k - 1)", "t[k - 1] = log_xi_pow(s->xi, k)"),
+    "pair force sign": ("g[(size_t)(l - 1) * D + a] += -2.0 * u * d * inv_s2;",
+                        "g[(size_t)(l - 1) * D + a] += 2.0 * u * d * inv_s2;"),
+    "bead index in Eq. 17": ("R(x, a, j + 1, l) - R(x, a, j - 1, l));", "R(x, a, j + 1, l) - R(x, a, j, l));"),
+    "primitive sign": ("- e->spring_expect + (ut + up)", "+ e->spring_expect + (ut + up)"),
+    "cycle energy factor k": ("double eps = 0.5 * (double)dim * (double)k / tanh(0.5 * kb);",
+                              "double eps = 0.5 * (double)dim / tanh(0.5 * kb);"),
+    "sign in Eq. 13": ("pr = 1.0 - exp(-(X[l] + Y[l + 1]) + XN);", "pr = 1.0 - exp(-(X[l] + Y[l + 1]) - XN);"),
+    "virial half": ("ks_add(&vir, 0.5 * R(x, a, j, l) * gr);", "ks_add(&vir, R(x, a, j, l) * gr);"),
+    "density binning": ("int b = (r >= rmax) ? bins : (int)(r / rmax * bins);",
+                        "int b = (r >= rmax) ? bins : (int)(r * r / rmax * bins);"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_fail_on_planted_mistake(name):
+    src = open(os.path.join(ROOT, "oracle", "pimd_oracle.c")).read()
+    old, new = MUTATIONS[name]
+    assert src.count(old) == 1, f"mutation anchor not found: {name}"
+    with tempfile.TemporaryDirectory() as d:
+        csrc = os.path.join(d, "pimd_oracle.c")
+        with open(csrc, "w") as fh:
+            fh.write(src.replace(old, new))
+        with open(os.path.join(d, "pimd_oracle.h"), "w") as fh:
+            fh.write(open(os.path.join(ROOT, "oracle", "pimd_oracle.h")).read())
+        lib = os.path.join(d, "liboracle.so")
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", lib, csrc, "-lm"])
+        env = dict(os.environ, PIMD_ORACLE_LIB=lib)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            "tests/test_oracle_pins.py", "tests/test_golden_paper.py"],
+                           cwd=ROOT, env=env, capture_output=True, text=True)
+    assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
