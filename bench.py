@@ -88,10 +88,9 @@ def algorithmic_work(kind, systems, P, D):
         # per ordered pair: D subtractions, D FMAs (|dr|^2), one exp, D FMAs (force) = 5D + 1 flops
         return "alu", npairs, 5 * D + 1, "TFLOP/s", PEAK_FP32_TFLOPS
     if kind == "recursion":
-        # two recursions, each N(N+1)/2 log-sum-exp terms: distance (3D) + 6 adds + exp (~20) ~ 30 flops
-        return "alu", 2 * tri, 3 * D + 26, "TFLOP/s", PEAK_FP64_TFLOPS
-    if kind == "probs":
-        return "alu", tri, 8 * D + 24, "TFLOP/s", PEAK_FP64_TFLOPS
+        # two recursions, each N(N+1)/2 terms; per term (FP64, FMA = 2): distance D + 2D, exponent 4,
+        # table exp 17, sum 1, payload sums 2(D+1)  ->  5D + 24 flops
+        return "alu", 2 * tri, 5 * D + 24, "TFLOP/s", PEAK_FP64_TFLOPS
     if kind in ("springs",):
         # read x, write f (8 B each per dof), plus end beads / links per particle (small)
         return "hbm", dofs, 16, "GB/s", PEAK_HBM_GBS
@@ -100,6 +99,9 @@ def algorithmic_work(kind, systems, P, D):
         return "hbm", dofs, 8 * (11 + 10), "GB/s", PEAK_HBM_GBS
     if kind == "integrate_second":
         return "hbm", dofs, 8 * (11 + 9), "GB/s", PEAK_HBM_GBS
+    if kind == "integrate_fused":
+        # read x, p, f, f_pair, eta[4], veta[4]; write x, p, f, eta[4], veta[4]
+        return "hbm", dofs, 8 * (12 + 11), "GB/s", PEAK_HBM_GBS
     return "hbm", dofs, 8, "GB/s", PEAK_HBM_GBS
 
 

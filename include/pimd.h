@@ -90,6 +90,12 @@ typedef struct {
     int32_t sy_order;        /* Suzuki-Yoshida order of the thermostat step: 1, 3 or 5       */
     int32_t density_bins;    /* radial density bins >= 1 (one extra overflow bin is kept)    */
     int32_t trace_capacity;  /* energy samples kept per replica (ring buffer), >= 0          */
+    int32_t recursion_workgroups; /* schedule of the exchange recursions (Eqs. 6, 11): 0 = chosen
+                                from the batch size and the device; 1 = one workgroup per replica
+                                and direction; k > 1 = one chain workgroup plus k-1 helpers that
+                                pre-sum finished column panels (cooperative launch; reduced to fit
+                                the device, or 1 if cooperative launch is unavailable)        */
+    int32_t reserved;        /* must be 0                                                    */
     double density_rmax;     /* radius covered by the bins > 0                               */
     const pimd_replica* replicas; /* n_replicas entries, copied by pimd_create              */
 } pimd_config;

@@ -3,8 +3,8 @@
 // A force evaluation of all replicas is, in order on the caller's stream:
 //   springs (interior/trap forces, end beads, links, E_int, FP32 shadow)
 //   -> [pair kernel on a second stream, joined before the integrator]
-//   -> forward+backward exchange recursion -> probability tiles -> per-particle reduction
-//      (end-bead forces, expected spring energy)
+//   -> forward+backward exchange recursions (potentials and the weighted row averages that
+//      stand in for the probability matrix) -> per-particle end-bead forces and spring energy
 // and an MD step wraps it in the two halves of the thermostatted velocity-Verlet step.
 #include <hip/hip_runtime.h>
 
@@ -36,9 +36,9 @@ pimd_status fail(pimd_status st, const std::string& msg) {
       return fail(PIMD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
-enum Kind { K_SPRINGS = 0, K_PAIR, K_RECURSION, K_PROBS, K_REDUCE, K_INT1, K_INT2, K_EST, K_DENS, K_COUNT };
-const char* kKindNames[K_COUNT] = {"springs", "pair", "recursion", "probs", "probs_reduce",
-                                   "integrate_first", "integrate_second", "estimators", "density"};
+enum Kind { K_SPRINGS = 0, K_PAIR, K_RECURSION, K_REDUCE, K_INT1, K_INT2, K_INTF, K_EST, K_DENS, K_COUNT };
+const char* kKindNames[K_COUNT] = {"springs", "pair", "recursion", "exchange_forces", "integrate_first",
+                                   "integrate_second", "integrate_fused", "estimators", "density"};
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
@@ -46,14 +46,15 @@ struct Plan {
   Dims d{};
   int jsplit = 1;
   std::vector<RepDev> reps;
-  std::vector<int4> springwork, pairwork, probwork;
+  std::vector<int4> springwork, pairwork, intwork;
   size_t off[32]{};
   size_t total = 0;
 };
 
-enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LINK, S_EINT, S_GF, S_GB, S_ROWP,
-           S_COLP, S_SPRINGP, S_PAIRP, S_REDP, S_REC, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_SPRINGW, S_PAIRW,
-           S_PROBW, S_DBG, S_COUNT };
+enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LINK, S_EINT, S_GF, S_GB, S_COLREC, S_AVG,
+           S_FLAGS, S_PARTIAL, S_ERR,
+           S_SPRINGP, S_PAIRP, S_REDP, S_REC, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_SPRINGW, S_PAIRW, S_INTW, S_DBG,
+           S_COUNT };
 
 pimd_status validate(const pimd_config* c) {
   if (!c) return fail(PIMD_ERR_INVALID, "config is NULL");
@@ -68,6 +69,9 @@ pimd_status validate(const pimd_config* c) {
   if (c->density_bins < 1 || c->density_bins > 4096) return fail(PIMD_ERR_INVALID, "density_bins must be in 1..4096");
   if (!(c->density_rmax > 0)) return fail(PIMD_ERR_INVALID, "density_rmax must be > 0");
   if (c->trace_capacity < 0) return fail(PIMD_ERR_INVALID, "trace_capacity must be >= 0");
+  if (c->recursion_workgroups < 0 || c->recursion_workgroups > 4096)
+    return fail(PIMD_ERR_INVALID, "recursion_workgroups must be in 0..4096");
+  if (c->reserved != 0) return fail(PIMD_ERR_INVALID, "reserved must be 0");
   for (int r = 0; r < c->n_replicas; ++r) {
     const pimd_replica& q = c->replicas[r];
     std::string where = "replica " + std::to_string(r) + ": ";
@@ -98,7 +102,7 @@ void make_plan(const pimd_config* c, Plan& pl) {
     if (c->replicas[r].pair_amp > 0) tiles64 += (long long)d.P * ((c->replicas[r].n + 63) / 64);
   pl.jsplit = tiles64 < 1024 ? 4 : (tiles64 < 2048 ? 2 : 1);
   const int ipw = 64 * (4 / pl.jsplit);  // particles per pair workgroup
-  long long G = 0, NP = 0, PROB = 0, XS = 0;
+  long long G = 0, NP = 0, XS = 0;
   int maxn = 0;
   pl.reps.resize(d.R);
   for (int r = 0; r < d.R; ++r) {
@@ -114,8 +118,6 @@ void make_plan(const pimd_config* c, Plan& pl) {
     G += round_up(R.ndof, 64);
     R.part = NP;
     NP += R.npp;
-    R.prob = PROB;
-    PROB += (long long)R.nblk * R.npp;
     R.shadow = XS;
     if (d.precision == PIMD_MIXED) XS += (long long)d.P * R.npad * dp;
     maxn = std::max(maxn, q.n);
@@ -138,14 +140,13 @@ void make_plan(const pimd_config* c, Plan& pl) {
       for (int j = 0; j < d.P; ++j)
         for (int i0 = 0; i0 < q.n; i0 += ipw) pl.pairwork.push_back(make_int4(r, j, i0, 0));
     R.pw1 = (long long)pl.pairwork.size();
-    for (int rb = 0; rb < R.nblk; ++rb)
-      for (int cb = 0; cb <= rb; ++cb) pl.probwork.push_back(make_int4(r, rb, cb, 0));
+    for (long long d0 = 0; d0 < R.ndof; d0 += kIntBlock) pl.intwork.push_back(make_int4(r, (int)d0, 0, 0));
   }
-  d.G = G; d.NPtot = NP; d.PROBtot = PROB; d.XStot = XS; d.maxn = maxn;
+  d.G = G; d.NPtot = NP; d.XStot = XS; d.maxn = maxn;
   d.nspringwg = (long long)pl.springwork.size();
   d.npairwork = (long long)pl.pairwork.size();
-  d.nprobwork = (long long)pl.probwork.size();
   d.nreducewg = d.nspringwg;
+  d.nintwg = (long long)pl.intwork.size();
   // segment sizes in bytes
   size_t sz[S_COUNT];
   sz[S_REPS] = sizeof(RepDev) * d.R;
@@ -154,7 +155,11 @@ void make_plan(const pimd_config* c, Plan& pl) {
   sz[S_ETA] = sz[S_VETA] = 8ull * G * d.M;
   sz[S_ENDS] = 8ull * 2 * d.D * NP;
   sz[S_LINK] = sz[S_EINT] = sz[S_GF] = sz[S_GB] = 8ull * NP;
-  sz[S_ROWP] = sz[S_COLP] = 8ull * (d.D + 2) * PROB;
+  sz[S_COLREC] = 32ull * 2 * NP;
+  sz[S_AVG] = 8ull * 2 * (d.D + 1) * NP;
+  sz[S_FLAGS] = 4ull * 4 * NP;
+  sz[S_PARTIAL] = 8ull * 2 * (d.D + 3) * NP;
+  sz[S_ERR] = 256;
   sz[S_SPRINGP] = 8ull * 4 * d.nspringwg;
   sz[S_PAIRP] = 8ull * 2 * std::max<long long>(d.npairwork, 1);
   sz[S_REDP] = 8ull * 2 * d.nreducewg;
@@ -165,7 +170,7 @@ void make_plan(const pimd_config* c, Plan& pl) {
   sz[S_DENSN] = 8ull * d.R;
   sz[S_SPRINGW] = sizeof(int4) * d.nspringwg;
   sz[S_PAIRW] = sizeof(int4) * std::max<long long>(d.npairwork, 1);
-  sz[S_PROBW] = sizeof(int4) * d.nprobwork;
+  sz[S_INTW] = sizeof(int4) * d.nintwg;
   sz[S_DBG] = 8ull * std::max<long long>(2LL * (maxn + 2), std::min<long long>((long long)maxn * maxn, 1LL << 20));
   size_t o = 0;
   for (int s = 0; s < S_COUNT; ++s) {
@@ -187,6 +192,8 @@ struct pimd_ctx {
   bool evaluated = false;
   long long step = 0;
   bool has_pair = false;
+  int helpers = 0;       // helper workgroups per recursion chain (0: one workgroup per chain)
+  int epoch = 0;         // stamp of the last cooperative recursion launch
   bool profiling = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof;
   std::vector<hipEvent_t> ev_pool;
@@ -259,8 +266,13 @@ pimd_status evaluate(pimd_ctx* c, bool est) {
     RUN(K_PAIR, ps, launch_pair(d, w, est, c->pl.jsplit, ps));
     if (fork) HIPCHK(hipEventRecord(c->ev_join, c->s2));
   }
-  RUN(K_RECURSION, c->s, launch_recursion(d, w, c->s));
-  RUN(K_PROBS, c->s, launch_probs(d, w, c->s));
+  if (c->helpers > 0) {
+    c->epoch = c->epoch == 0x7fffffff ? 1 : c->epoch + 1;
+    const int ep = c->epoch;
+    RUN(K_RECURSION, c->s, launch_recursion_coop(d, w, c->helpers, ep, c->s));
+  } else {
+    RUN(K_RECURSION, c->s, launch_recursion(d, w, c->s));
+  }
   RUN(K_REDUCE, c->s, launch_probs_reduce(d, w, c->s));
   if (fork) HIPCHK(hipStreamWaitEvent(c->s, c->ev_join, 0));
   return PIMD_OK;
@@ -283,6 +295,19 @@ hipMemcpyKind kind_in(pimd_mem m) { return m == PIMD_DEVICE ? hipMemcpyDeviceToD
 hipMemcpyKind kind_out(pimd_mem m) { return m == PIMD_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
 
 }  // namespace
+
+static pimd_status check_device_error(pimd_ctx* c) {
+  int e = 0;
+  HIPCHK(hipMemcpyAsync(&e, c->w.err, sizeof(int), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (e != 0) {
+    int z = 0;
+    HIPCHK(hipMemcpyAsync(c->w.err, &z, sizeof(int), hipMemcpyHostToDevice, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    return fail(PIMD_ERR_DEVICE, "a wait of the cooperative exchange recursion timed out; results are invalid");
+  }
+  return PIMD_OK;
+}
 
 extern "C" {
 
@@ -329,8 +354,11 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   w.eint = (double*)(c->ws + off[S_EINT]);
   w.gf = (double*)(c->ws + off[S_GF]);
   w.gb = (double*)(c->ws + off[S_GB]);
-  w.rowpart = (double*)(c->ws + off[S_ROWP]);
-  w.colpart = (double*)(c->ws + off[S_COLP]);
+  w.colrec = (double4*)(c->ws + off[S_COLREC]);
+  w.avg = (double*)(c->ws + off[S_AVG]);
+  w.flags = (int*)(c->ws + off[S_FLAGS]);
+  w.partial = (double*)(c->ws + off[S_PARTIAL]);
+  w.err = (int*)(c->ws + off[S_ERR]);
   w.springpart = (double*)(c->ws + off[S_SPRINGP]);
   w.pairpart = (double*)(c->ws + off[S_PAIRP]);
   w.reducepart = (double*)(c->ws + off[S_REDP]);
@@ -341,8 +369,8 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   w.denssamples = (long long*)(c->ws + off[S_DENSN]);
   w.springwork = (int4*)(c->ws + off[S_SPRINGW]);
   w.pairwork = (int4*)(c->ws + off[S_PAIRW]);
-  w.probwork = (int4*)(c->ws + off[S_PROBW]);
   w.reducework = w.springwork;
+  w.intwork = (int4*)(c->ws + off[S_INTW]);
   w.dbg = (double*)(c->ws + off[S_DBG]);
   for (auto& r : c->pl.reps) c->has_pair = c->has_pair || r.amp > 0;
   auto cleanup = [&](pimd_status s2) {
@@ -358,13 +386,34 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
     e = hipMemcpyAsync(w.springwork, c->pl.springwork.data(), sizeof(int4) * c->pl.springwork.size(), hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess && !c->pl.pairwork.empty())
     e = hipMemcpyAsync(w.pairwork, c->pl.pairwork.data(), sizeof(int4) * c->pl.pairwork.size(), hipMemcpyHostToDevice, c->s);
-  if (e == hipSuccess && !c->pl.probwork.empty())
-    e = hipMemcpyAsync(w.probwork, c->pl.probwork.data(), sizeof(int4) * c->pl.probwork.size(), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess && !c->pl.intwork.empty())
+    e = hipMemcpyAsync(w.intwork, c->pl.intwork.data(), sizeof(int4) * c->pl.intwork.size(), hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) return cleanup(fail(PIMD_ERR_DEVICE, std::string("pimd_create: ") + hipGetErrorString(e)));
+  // Schedule of the exchange recursions: cooperative chain + helpers when a few replicas would
+  // otherwise leave most of the device idle.
+  {
+    int dev = 0, cus = 0, coop = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop) {
+      const int per_cu = recursion_coop_max_blocks_per_cu(c->pl.d.D);
+      const long long nchains = 2LL * c->pl.d.R;
+      const long long capacity = (long long)per_cu * cus;
+      int max_nblk = 0;
+      for (auto& r : c->pl.reps) max_nblk = std::max(max_nblk, (r.n + 1 + kTile - 1) / kTile);
+      const long long useful = std::max(0, max_nblk - 2);
+      long long H = 0;
+      const int req = cfg->recursion_workgroups;
+      if (req > 1) H = req - 1;
+      else if (req == 0 && nchains * 4 <= cus && useful > 0) H = capacity / nchains - 1;
+      H = std::min(H, useful);
+      if (nchains * (1 + H) > capacity) H = capacity / nchains - 1;
+      c->helpers = (int)std::max(0LL, H);
+    }
+  }
   *out = c;
   return PIMD_OK;
 }
@@ -443,6 +492,7 @@ pimd_status pimd_get_forces(pimd_ctx* c, int32_t r, double* f, pimd_mem where) {
   if (st != PIMD_OK) return st;
   if (!f) return fail(PIMD_ERR_INVALID, "f is NULL");
   if (!c->forces_valid) return fail(PIMD_ERR_STATE, "no force evaluation since the last set_state");
+  if ((st = check_device_error(c)) != PIMD_OK) return st;
   const RepDev& R = c->pl.reps[r];
   HIPCHK(hipMemcpyAsync(f, c->w.f + R.dof, sizeof(double) * (size_t)R.ndof, kind_out(where), c->s));
   HIPCHK(hipStreamSynchronize(c->s));
@@ -459,15 +509,26 @@ pimd_status pimd_step(pimd_ctx* c, int64_t n_steps, int32_t sample_every) {
     RUN(K_INT2, c->s, launch_integrate_second(d, c->w, false, c->s));
     c->forces_valid = true;
   }
+  // Step k: [first half] evaluate [second half].  The second half of step k and the first
+  // half of step k+1 run as one fused pass unless step k is sampled (the estimators need the
+  // state between the halves) or k is the last step of this call.
+  bool pending_first = true;
   for (int64_t it = 0; it < n_steps; ++it) {
     const bool smp = sample_every > 0 && ((c->step + 1) % sample_every == 0);
-    RUN(K_INT1, c->s, launch_integrate_first(d, c->w, c->s));
+    if (pending_first) RUN(K_INT1, c->s, launch_integrate_first(d, c->w, c->s));
     if ((st = evaluate(c, smp)) != PIMD_OK) return st;
-    RUN(K_INT2, c->s, launch_integrate_second(d, c->w, true, c->s));
     c->step += 1;
-    if (smp) {
-      if ((st = sample(c, true)) != PIMD_OK) return st;
-      c->evaluated = true;
+    const bool last = (it + 1 == n_steps);
+    if (smp || last) {
+      RUN(K_INT2, c->s, launch_integrate_second(d, c->w, true, c->s));
+      if (smp) {
+        if ((st = sample(c, true)) != PIMD_OK) return st;
+        c->evaluated = true;
+      }
+      pending_first = true;
+    } else {
+      RUN(K_INTF, c->s, launch_integrate_fused(d, c->w, c->s));
+      pending_first = false;
     }
   }
   return PIMD_OK;
@@ -483,6 +544,7 @@ pimd_status pimd_energies(pimd_ctx* c, int32_t r, pimd_estimates* out) {
   pimd_status st = check_ctx_r(c, r);
   if (st != PIMD_OK) return st;
   if (!out) return fail(PIMD_ERR_INVALID, "out is NULL");
+  if ((st = check_device_error(c)) != PIMD_OK) return st;
   double o[kRec];
   HIPCHK(hipMemcpyAsync(o, c->w.rec + (long long)kRec * r, sizeof(o), hipMemcpyDeviceToHost, c->s));
   HIPCHK(hipStreamSynchronize(c->s));

@@ -9,33 +9,39 @@
 // All of it is FP64 and elementwise over degrees of freedom (HBM-bound).
 #include "pimd_internal.h"
 #include "device_util.h"
+#include "fast_exp.h"
 
 namespace pimd {
 
 struct SyW { double w[5]; int n; };
 
-__device__ inline void nhc_propagate(double& p, double mp, double* eta, double* v, int M, double Q, double kT,
-                                     double tau, const SyW& sy) {
+// The chain forces are G_1 = (p^2/m' - kT)/Q and G_k = (Q v_{k-1}^2 - kT)/Q = v_{k-1}^2 - kT/Q,
+// evaluated with precomputed reciprocals.  The scale factor exp(-h v_{k+1}/4) of element k is
+// the same number in the inward and the outward sweep (v_{k+1} is not touched in between), so
+// it is computed once per sub-step.
+__device__ inline void nhc_propagate(double& p, double inv_mp, double* eta, double* v, int M, double inv_q,
+                                     double kT, double tau, const SyW& sy, const double* tab) {
+  const double kTq = kT * inv_q;
   for (int iw = 0; iw < sy.n; ++iw) {
     const double h = sy.w[iw] * tau;
+    double sc[kMaxNhc];
     {
-      double Gm = (M == 1) ? (p * p / mp - kT) / Q : (Q * v[M - 2] * v[M - 2] - kT) / Q;
+      double Gm = (M == 1) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[M - 2], v[M - 2], -kTq);
       v[M - 1] += 0.5 * h * Gm;
     }
     for (int k = M - 2; k >= 0; --k) {
-      double sc = exp(-0.25 * h * v[k + 1]);
-      double Gk = (k == 0) ? (p * p / mp - kT) / Q : (Q * v[k - 1] * v[k - 1] - kT) / Q;
-      v[k] = (v[k] * sc + 0.5 * h * Gk) * sc;
+      sc[k] = fast_exp(-0.25 * h * v[k + 1], tab);
+      double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
+      v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];
     }
-    p *= exp(-h * v[0]);
+    p *= fast_exp(-h * v[0], tab);
     for (int k = 0; k < M; ++k) eta[k] += h * v[k];
     for (int k = 0; k <= M - 2; ++k) {
-      double sc = exp(-0.25 * h * v[k + 1]);
-      double Gk = (k == 0) ? (p * p / mp - kT) / Q : (Q * v[k - 1] * v[k - 1] - kT) / Q;
-      v[k] = (v[k] * sc + 0.5 * h * Gk) * sc;
+      double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
+      v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];
     }
     {
-      double Gm = (M == 1) ? (p * p / mp - kT) / Q : (Q * v[M - 2] * v[M - 2] - kT) / Q;
+      double Gm = (M == 1) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[M - 2], v[M - 2], -kTq);
       v[M - 1] += 0.5 * h * Gm;
     }
   }
@@ -43,69 +49,75 @@ __device__ inline void nhc_propagate(double& p, double mp, double* eta, double* 
 
 template <int M>
 __device__ inline void nhc_half(double& p, const RepDev& R, double* eta, double* veta, long long gi, long long G,
-                                const SyW& sy) {
+                                const SyW& sy, const double* tab) {
   if (M == 0) return;
   double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
 #pragma unroll
   for (int k = 0; k < M; ++k) { e[k] = eta[k * G + gi]; v[k] = veta[k * G + gi]; }
-  nhc_propagate(p, R.mp, e, v, M, R.q, 1.0 / R.beta, 0.5 * R.dt, sy);
+  nhc_propagate(p, 1.0 / R.mp, e, v, M, 1.0 / R.q, 1.0 / R.beta, 0.5 * R.dt, sy, tab);
 #pragma unroll
   for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
 }
 
-// Thread -> degree of freedom; the spring work list doubles as the dof work list
-// (workgroup g covers dofs [l0*D*P, ...) of its replica in chunks of 256 particles).
-template <int M>
-__global__ __launch_bounds__(256) void k_integrate_first(const RepDev* __restrict__ reps,
+// Thread -> degree of freedom.  Work item {rep, first dof} covers kIntBlock consecutive dofs of
+// one replica; dofs are elementwise-independent, so the launch is a flat coalesced stream.
+// mode 0: first half  (NHC(dt/2), p += F dt/2, x += p dt/m')
+// mode 1: second half (F = F + F_pair, then p += F dt/2, NHC(dt/2))
+// mode 2: F = F + F_pair only (force evaluation without integration)
+// mode 3: second half of this step fused with the first half of the next one
+template <int M, int MODE>
+__global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restrict__ reps,
                                                          const int4* __restrict__ work, double* __restrict__ x,
-                                                         double* __restrict__ p, const double* __restrict__ f,
-                                                         double* __restrict__ eta, double* __restrict__ veta,
-                                                         long long G, int DP, SyW sy) {
+                                                         double* __restrict__ p, double* __restrict__ f,
+                                                         const double* __restrict__ fpair, double* __restrict__ eta,
+                                                         double* __restrict__ veta, long long G, SyW sy) {
+  __shared__ double tab[kExpTable];
+  if (M > 0 && MODE != 2) {
+    if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
+    __syncthreads();
+  }
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
-  const long long nd = R.ndof;
-  // each workgroup of the spring list owns 256 particles; as a dof list it owns DP*256 dofs
-  const long long base = (long long)wk.y * DP;
-  for (int k = 0; k < DP; ++k) {
-    const long long li = base + (long long)k * 256 + threadIdx.x;
-    if (li >= nd) break;
-    const long long gi = R.dof + li;
+  const long long li = (long long)wk.y + threadIdx.x;
+  if (li >= R.ndof) return;
+  const long long gi = R.dof + li;
+  const double hdt = 0.5 * R.dt;
+  if (MODE == 0) {
     double pv = p[gi];
-    nhc_half<M>(pv, R, eta, veta, gi, G, sy);
-    pv += 0.5 * R.dt * f[gi];
+    nhc_half<M>(pv, R, eta, veta, gi, G, sy, tab);
+    pv += hdt * f[gi];
     x[gi] += R.dt * pv / R.mp;
     p[gi] = pv;
+    return;
   }
-}
-
-template <int M>
-__global__ __launch_bounds__(256) void k_integrate_second(const RepDev* __restrict__ reps,
-                                                          const int4* __restrict__ work, double* __restrict__ p,
-                                                          double* __restrict__ f, const double* __restrict__ fpair,
-                                                          double* __restrict__ eta, double* __restrict__ veta,
-                                                          long long G, int DP, SyW sy, int kick) {
-  const int4 wk = work[blockIdx.x];
-  const RepDev& R = reps[wk.x];
-  const long long nd = R.ndof;
-  const long long base = (long long)wk.y * DP;
-  const bool pair = R.amp > 0.0;
-  for (int k = 0; k < DP; ++k) {
-    const long long li = base + (long long)k * 256 + threadIdx.x;
-    if (li >= nd) break;
-    const long long gi = R.dof + li;
-    double fv = f[gi];
-    if (pair) fv += fpair[gi];
-    f[gi] = fv;
-    if (kick) {
-      double pv = p[gi] + 0.5 * R.dt * fv;
-      nhc_half<M>(pv, R, eta, veta, gi, G, sy);
-      p[gi] = pv;
-    }
+  double fv = f[gi];
+  if (R.amp > 0.0) fv += fpair[gi];
+  f[gi] = fv;
+  if (MODE == 2) return;
+  double pv = p[gi] + hdt * fv;
+  if (MODE == 1) {
+    nhc_half<M>(pv, R, eta, veta, gi, G, sy, tab);
+    p[gi] = pv;
+    return;
   }
+  // MODE 3: both thermostat half-steps on the chain held in registers
+  if (M > 0) {
+    double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
+#pragma unroll
+    for (int k = 0; k < M; ++k) { e[k] = eta[k * G + gi]; v[k] = veta[k * G + gi]; }
+    const double inv_mp = 1.0 / R.mp, inv_q = 1.0 / R.q, kT = 1.0 / R.beta;
+    nhc_propagate(pv, inv_mp, e, v, M, inv_q, kT, hdt, sy, tab);
+    nhc_propagate(pv, inv_mp, e, v, M, inv_q, kT, hdt, sy, tab);
+#pragma unroll
+    for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
+  }
+  pv += hdt * fv;
+  x[gi] += R.dt * pv / R.mp;
+  p[gi] = pv;
 }
 
 // One workgroup per replica: kinetic and thermostat energies over all dofs plus the
-// partial sums left by the spring, pair and probability kernels, in a fixed order.
+// partial sums left by the spring, pair and end-bead kernels, in a fixed order.
 __global__ __launch_bounds__(256) void k_estimators(const RepDev* __restrict__ reps, const double* __restrict__ p,
                                                     const double* __restrict__ eta, const double* __restrict__ veta,
                                                     const double* __restrict__ gf,
@@ -227,13 +239,13 @@ static SyW sy_weights(int order) {
   return s;
 }
 
-hipError_t launch_integrate_first(const Dims& d, const DevPtrs& w, hipStream_t s) {
-  if (d.nspringwg == 0) return hipSuccess;
-  dim3 grid((unsigned)d.nspringwg), block(256);
+template <int MODE>
+static hipError_t launch_integrate_mode(const Dims& d, const DevPtrs& w, hipStream_t s) {
+  if (d.nintwg == 0) return hipSuccess;
+  dim3 grid((unsigned)d.nintwg), block(kIntBlock);
   const SyW sy = sy_weights(d.sy_order);
-  const int DP = d.D * d.P;
-#define L(MM) hipLaunchKernelGGL(k_integrate_first<MM>, grid, block, 0, s, w.reps, w.springwork, w.x, w.p, w.f, \
-                                 w.eta, w.veta, d.G, DP, sy)
+#define L(MM) hipLaunchKernelGGL((k_integrate<MM, MODE>), grid, block, 0, s, w.reps, w.intwork, w.x, w.p, w.f, \
+                                 w.fpair, w.eta, w.veta, d.G, sy)
   switch (d.M) {
     case 0: L(0); break; case 1: L(1); break; case 2: L(2); break; case 3: L(3); break;
     case 4: L(4); break; case 5: L(5); break; case 6: L(6); break; case 7: L(7); break; case 8: L(8); break;
@@ -243,20 +255,16 @@ hipError_t launch_integrate_first(const Dims& d, const DevPtrs& w, hipStream_t s
   return hipGetLastError();
 }
 
+hipError_t launch_integrate_first(const Dims& d, const DevPtrs& w, hipStream_t s) {
+  return launch_integrate_mode<0>(d, w, s);
+}
+
 hipError_t launch_integrate_second(const Dims& d, const DevPtrs& w, bool kick, hipStream_t s) {
-  if (d.nspringwg == 0) return hipSuccess;
-  dim3 grid((unsigned)d.nspringwg), block(256);
-  const SyW sy = sy_weights(d.sy_order);
-  const int DP = d.D * d.P;
-#define L(MM) hipLaunchKernelGGL(k_integrate_second<MM>, grid, block, 0, s, w.reps, w.springwork, w.p, w.f, \
-                                 w.fpair, w.eta, w.veta, d.G, DP, sy, kick ? 1 : 0)
-  switch (d.M) {
-    case 0: L(0); break; case 1: L(1); break; case 2: L(2); break; case 3: L(3); break;
-    case 4: L(4); break; case 5: L(5); break; case 6: L(6); break; case 7: L(7); break; case 8: L(8); break;
-    default: return hipErrorInvalidValue;
-  }
-#undef L
-  return hipGetLastError();
+  return kick ? launch_integrate_mode<1>(d, w, s) : launch_integrate_mode<2>(d, w, s);
+}
+
+hipError_t launch_integrate_fused(const Dims& d, const DevPtrs& w, hipStream_t s) {
+  return launch_integrate_mode<3>(d, w, s);
 }
 
 hipError_t launch_estimators(const Dims& d, const DevPtrs& w, long long step, bool record, hipStream_t s) {

@@ -13,6 +13,7 @@ constexpr int kTile = 64;          // rows/columns of one exchange tile (= wavef
 constexpr int kMaxNhc = 8;         // longest thermostat chain
 constexpr int kRec = 16;           // doubles per energy record
 constexpr int kSpringBlock = 256;  // particles per spring-kernel workgroup
+constexpr int kIntBlock = 256;     // degrees of freedom per integrator workgroup
 
 // Energy record slots (per replica, and per trace sample).
 enum RecSlot {
@@ -29,7 +30,6 @@ struct RepDev {
   long long dof;    // offset of this replica's x, p, f, fpair block ([dim][P][N], contiguous)
   long long ndof;   // dim * P * N
   long long part;   // offset unit for particle arrays (sum of npp of earlier replicas)
-  long long prob;   // offset unit for probability partials (sum of nblk*npp of earlier replicas)
   long long shadow; // offset of the FP32 shadow ([P][npad][dp] floats)
   long long spw0, spw1;    // spring workgroups [spw0, spw1)
   long long pw0, pw1;      // pair work items [pw0, pw1)
@@ -52,7 +52,11 @@ struct DevPtrs {
   double* link;                // [npp]: c |b_l - a_{l+1}|^2, 0 for the last particle
   double* eint;                // [npp]: internal spring energy of each ring
   double* gf; double* gb;      // [npp]: forward / backward normalised log-potentials, rows 0..N
-  double* rowpart; double* colpart;  // [(dim+2)][nblk][npp] per replica
+  double4* colrec;             // [2][npp] per replica: recursion column records {q_j, colc_j + G_j}
+  double* avg;                 // [2][dim+1][npp] per replica: weighted row averages of the recursions
+  int* flags;                  // [4][npp] per replica: panel / partial ready flags (epochs), per direction
+  double* partial;             // [2][dim+3][npp] per replica: helper partial sums (m, s, payloads)
+  int* err;                    // error word raised by a timed-out wait
   double* springpart;          // [nspringwg][4]
   double* pairpart;            // [npairwork][2]
   double* reducepart;          // [nreducewg][2]
@@ -63,8 +67,8 @@ struct DevPtrs {
   long long* denssamples;      // [R]
   int4* springwork;            // {rep, l0, 0, 0}
   int4* pairwork;              // {rep, slice, i0, 0}
-  int4* probwork;              // {rep, rb, cb, 0}
   int4* reducework;            // {rep, l0, 0, 0}
+  int4* intwork;               // {rep, first dof, 0, 0}
   double* dbg;                 // debug scratch (N+2 doubles of the largest replica, x2)
 };
 
@@ -73,9 +77,8 @@ struct Dims {
   double rmax;
   long long G;                 // total dof (padded)
   long long NPtot;             // sum of npp
-  long long PROBtot;           // sum of nblk*npp
   long long XStot;             // floats in the shadow
-  long long nspringwg, npairwork, nprobwork, nreducewg;
+  long long nspringwg, npairwork, nreducewg, nintwg;
   int maxn;
 };
 
@@ -85,10 +88,12 @@ __host__ __device__ inline int shadow_dp(int D) { return D == 3 ? 4 : D; }
 hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool estimators, int jsplit, hipStream_t s);
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s);
-hipError_t launch_probs(const Dims& d, const DevPtrs& w, hipStream_t s);
+hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, int epoch, hipStream_t s);
+int recursion_coop_max_blocks_per_cu(int D);
 hipError_t launch_probs_reduce(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_integrate_first(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_integrate_second(const Dims& d, const DevPtrs& w, bool kick, hipStream_t s);
+hipError_t launch_integrate_fused(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_estimators(const Dims& d, const DevPtrs& w, long long step, bool record, hipStream_t s);
 hipError_t launch_density(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_debug_potentials(const Dims& d, const DevPtrs& w, int r, double* X, double* Y, hipStream_t s);

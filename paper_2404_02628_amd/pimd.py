@@ -41,7 +41,8 @@ class pimd_replica(C.Structure):
 class pimd_config(C.Structure):
     _fields_ = [("n_replicas", C.c_int32), ("p", C.c_int32), ("dim", C.c_int32), ("precision", C.c_int32),
                 ("nhc_len", C.c_int32), ("sy_order", C.c_int32), ("density_bins", C.c_int32),
-                ("trace_capacity", C.c_int32), ("density_rmax", C.c_double),
+                ("trace_capacity", C.c_int32), ("recursion_workgroups", C.c_int32), ("reserved", C.c_int32),
+                ("density_rmax", C.c_double),
                 ("replicas", C.POINTER(pimd_replica))]
 
 
@@ -232,7 +233,7 @@ class Context:
 
     def __init__(self, systems: Sequence[System], precision: str = "mixed", nhc_len: Optional[int] = None,
                  sy_order: int = 3, density_bins: int = 64, density_rmax: float = 6.0, trace_capacity: int = 0,
-                 device: str = "cuda:0"):
+                 recursion_workgroups: int = 0, device: str = "cuda:0"):
         import torch  # device memory and streams only
 
         if not systems:
@@ -251,7 +252,7 @@ class Context:
         m = systems[0].nhc_len if nhc_len is None else nhc_len
         self.nhc_len = m
         self.cfg = pimd_config(len(systems), p, dim, PIMD_MIXED if precision == "mixed" else PIMD_FP64, m,
-                               sy_order, density_bins, trace_capacity, density_rmax, reps)
+                               sy_order, density_bins, trace_capacity, recursion_workgroups, 0, density_rmax, reps)
         self.nbytes = pimd_workspace_bytes(self.cfg)
         self.device = torch.device(device)
         with torch.cuda.device(self.device):

@@ -88,14 +88,20 @@ def _check_against_oracle(orc, ctx, r, s, x, mixed):
     assert abs(en["e_vir"] - en_or["e_vir"]) <= tol_u * max(abs(en_or["e_vir"]), 1e-300)
 
 
+# recursion schedule: 1 = one workgroup per chain, 0 = automatic (cooperative chain + helpers
+# for a single replica with more than two row blocks), 5 = chain + 4 helpers
+SCHEDULES = [1, 0, 5]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=[f"wg{k}" for k in SCHEDULES])
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("case", CASES, ids=[f"N{c[0]}P{c[1]}d{c[2]}xi{c[4]}A{c[5]}" for c in CASES])
-def test_single_replica_matches_oracle(orc, case, mixed):
+def test_single_replica_matches_oracle(orc, case, mixed, sched):
     from paper_2404_02628_amd.pimd import Context
     n, p, d, beta, xi, A, s_, sigma, seed = case
     s = System(n=n, p=p, dim=d, beta=beta, xi=xi, pair_amp=A, pair_width=s_, sigma=sigma, seed=seed)
     x = random_positions(n, p, d, sigma, seed)
-    ctx = Context([s], precision="mixed" if mixed else "fp64")
+    ctx = Context([s], precision="mixed" if mixed else "fp64", recursion_workgroups=sched)
     try:
         ctx.set_state(0, x)
         ctx.compute_forces()
@@ -104,25 +110,28 @@ def test_single_replica_matches_oracle(orc, case, mixed):
         ctx.close()
 
 
+@pytest.mark.parametrize("sched", [1, 0], ids=["wg1", "auto"])
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
-def test_batched_uneven_replicas_match_oracle(orc, mixed):
+def test_batched_uneven_replicas_match_oracle(orc, mixed, sched):
     """Replicas of different N, xi and pair strength advance in one context; each equals
-    the oracle on its own configuration, and in FP64 equals the same replica run alone."""
+    the oracle on its own configuration, and in FP64 with one workgroup per chain it equals the
+    same replica run alone bit for bit."""
     from paper_2404_02628_amd.pimd import Context
     specs = [(5, 0.2, 1.0), (64, 0.4, 0.0), (65, 0.6, 1.0), (130, 0.8, 2.0), (200, 1.0, 1.0), (1, 1.0, 0.0)]
     systems = [System(n=n, p=8, dim=2, beta=3.0, xi=xi, pair_amp=A, pair_width=0.5, sigma=1.0, seed=50 + k)
                for k, (n, xi, A) in enumerate(specs)]
     xs = [random_positions(s.n, s.p, s.dim, s.sigma, s.seed) for s in systems]
-    ctx = Context(systems, precision="mixed" if mixed else "fp64")
+    ctx = Context(systems, precision="mixed" if mixed else "fp64", recursion_workgroups=sched)
     try:
         for r, x in enumerate(xs):
             ctx.set_state(r, x)
         ctx.compute_forces()
         for r, (s, x) in enumerate(zip(systems, xs)):
             _check_against_oracle(orc, ctx, r, s, x, mixed)
-        if not mixed:
+        if not mixed and sched == 1:
+            # same schedule, same summation order: a replica in the batch equals it run alone
             for r in (0, 3):
-                solo = Context([systems[r]], precision="fp64")
+                solo = Context([systems[r]], precision="fp64", recursion_workgroups=1)
                 solo.set_state(0, xs[r])
                 solo.compute_forces()
                 assert np.array_equal(solo.forces(0), ctx.forces(r))
@@ -131,9 +140,10 @@ def test_batched_uneven_replicas_match_oracle(orc, mixed):
         ctx.close()
 
 
+@pytest.mark.parametrize("sched", [1, 0], ids=["wg1", "auto"])
 @pytest.mark.parametrize("start", ["seeded", "thermal"])
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
-def test_large_gauss_workload_matches_oracle(orc, mixed, start):
+def test_large_gauss_workload_matches_oracle(orc, mixed, start, sched):
     """N=1600, P=32, d=2, A=0.5, s=0.5: the seeded N(0, 2^2) start of the benchmark, and
     thermal rings (equilibrium bead statistics) around N(0, 2^2) centroids."""
     from paper_2404_02628_amd.pimd import Context
@@ -143,7 +153,7 @@ def test_large_gauss_workload_matches_oracle(orc, mixed, start):
         x, _ = initial_state(s)
     else:
         x = thermal_rings(s.n, s.p, s.dim, s.beta, s.sigma, s.seed)
-    ctx = Context([s], precision="mixed" if mixed else "fp64")
+    ctx = Context([s], precision="mixed" if mixed else "fp64", recursion_workgroups=sched)
     try:
         ctx.set_state(0, x)
         ctx.compute_forces()
@@ -235,3 +245,30 @@ def test_nonfinite_state_is_reported(orc):
         assert ei.value.code == PIMD_ERR_NONFINITE
     finally:
         ctx.close()
+
+
+def test_schedules_agree_and_repeat(orc):
+    """The cooperative schedule (chain + helpers) and the one-workgroup schedule give the same
+    forces and potentials to rounding, and repeated evaluations (new epochs) repeat exactly."""
+    from paper_2404_02628_amd.pimd import Context
+    from paper_2404_02628_amd.workloads import thermal_rings
+    s = System(n=700, p=8, dim=3, beta=2.0, xi=0.6, pair_amp=1.0, pair_width=0.5, sigma=2.0, seed=31)
+    x = thermal_rings(s.n, s.p, s.dim, s.beta, s.sigma, s.seed)
+    out = {}
+    for sched in (1, 3, 12):
+        ctx = Context([s], precision="fp64", recursion_workgroups=sched)
+        try:
+            ctx.set_state(0, x)
+            ctx.compute_forces()
+            f1 = ctx.forces(0)
+            X1, Y1 = ctx.potentials(0)
+            ctx.compute_forces()
+            f2 = ctx.forces(0)
+            assert np.array_equal(f1, f2)
+            out[sched] = (f1, X1, Y1)
+        finally:
+            ctx.close()
+    for sched in (3, 12):
+        assert rel_max(out[sched][0], out[1][0]) <= 1e-12
+        assert rel_max(out[sched][1], out[1][1]) <= 1e-13
+        assert rel_max(out[sched][2][1:], out[1][2][1:]) <= 1e-13
