@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define PIMD_ABI_VERSION 1
+#define PIMD_ABI_VERSION 2
 
 typedef enum {
     PIMD_OK = 0,
@@ -63,6 +63,9 @@ typedef enum {
 } pimd_precision;
 
 typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
+
+/* pimd_config.flags */
+#define PIMD_FLAG_GRAPH 1      /* replay steady MD steps from a captured HIP graph (default: direct launches) */
 
 /* One independent system (replica).  Units are free; the paper uses
  * hbar = m = omega = k_B = 1 (Sec. IV.A). */
@@ -95,7 +98,7 @@ typedef struct {
                                 and direction; k > 1 = one chain workgroup plus k-1 helpers that
                                 pre-sum finished column panels (cooperative launch; reduced to fit
                                 the device, or 1 if cooperative launch is unavailable)        */
-    int32_t reserved;        /* must be 0                                                    */
+    int32_t flags;           /* PIMD_FLAG_* bits; all other bits must be 0                   */
     double density_rmax;     /* radius covered by the bins > 0                               */
     const pimd_replica* replicas; /* n_replicas entries, copied by pimd_create              */
 } pimd_config;
@@ -165,8 +168,20 @@ pimd_status pimd_get_forces(pimd_ctx* ctx, int32_t r, double* f, pimd_mem where)
  * x += p dt/m', F = force(x), p += F dt/2, NHC(dt/2).  The estimators, the
  * density histogram and the trace are taken every `sample_every` steps
  * (0 = never).  The first call evaluates the forces of the initial state.
- * Enqueued only.  Errors: PIMD_ERR_INVALID (n_steps < 0, sample_every < 0). */
+ * Enqueued only.  Errors: PIMD_ERR_INVALID (n_steps < 0, sample_every < 0).
+ * Steps that are neither sampled nor the first or last of the call are all the
+ * same launch sequence (evaluation plus the fused second/first integrator
+ * halves); with PIMD_FLAG_GRAPH (and profiling off) that sequence is captured
+ * once into a HIP graph and replayed on the stream.  If the device cannot
+ * capture it, the steps run by direct launches (pimd_graph_info).  Replay cuts
+ * host launch cost but runs the pair kernel and the recursions one after the
+ * other instead of on two streams, so it pays only for small systems. */
 pimd_status pimd_step(pimd_ctx* ctx, int64_t n_steps, int32_t sample_every);
+
+/* State of the step graph: *state = 0 not built yet, 1 built and replayed,
+ * 2 not requested (no PIMD_FLAG_GRAPH), 3 capture failed (direct launches);
+ * *replays = steps run by graph replay so far.  Either pointer may be NULL. */
+pimd_status pimd_graph_info(pimd_ctx* ctx, int32_t* state, int64_t* replays);
 
 /* Estimators of replica r from its most recent sampled evaluation (every
  * pimd_compute_forces samples).  Synchronises.  Errors: PIMD_ERR_STATE if none

@@ -71,7 +71,7 @@ pimd_status validate(const pimd_config* c) {
   if (c->trace_capacity < 0) return fail(PIMD_ERR_INVALID, "trace_capacity must be >= 0");
   if (c->recursion_workgroups < 0 || c->recursion_workgroups > 4096)
     return fail(PIMD_ERR_INVALID, "recursion_workgroups must be in 0..4096");
-  if (c->reserved != 0) return fail(PIMD_ERR_INVALID, "reserved must be 0");
+  if ((c->flags & ~PIMD_FLAG_GRAPH) != 0) return fail(PIMD_ERR_INVALID, "unknown bits in flags");
   for (int r = 0; r < c->n_replicas; ++r) {
     const pimd_replica& q = c->replicas[r];
     std::string where = "replica " + std::to_string(r) + ": ";
@@ -193,7 +193,10 @@ struct pimd_ctx {
   long long step = 0;
   bool has_pair = false;
   int helpers = 0;       // helper workgroups per recursion chain (0: one workgroup per chain)
-  int epoch = 0;         // stamp of the last cooperative recursion launch
+  hipStream_t sc = nullptr;          // stream the step graph is captured on
+  hipGraphExec_t gexec = nullptr;    // one steady MD step (evaluation + fused integrator halves)
+  int graph_state = 0;               // 0 not built, 1 built, 2 not requested, 3 capture failed
+  long long graph_replays = 0;
   bool profiling = false;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof;
   std::vector<hipEvent_t> ev_pool;
@@ -251,31 +254,52 @@ pimd_status timed(pimd_ctx* c, int kind, hipStream_t st, F&& launch) {
     if (r_ != PIMD_OK) return r_;                                \
   } while (0)
 
-// One force evaluation of every replica at the current positions.
-pimd_status evaluate(pimd_ctx* c, bool est) {
+// One force evaluation of every replica at the current positions, enqueued on stream ms.
+pimd_status evaluate(pimd_ctx* c, bool est, hipStream_t ms) {
   const Dims& d = c->pl.d;
   const DevPtrs& w = c->w;
-  RUN(K_SPRINGS, c->s, launch_springs(d, w, c->s));
+  RUN(K_SPRINGS, ms, launch_springs(d, w, ms));
   const bool fork = c->has_pair && !c->profiling;
-  hipStream_t ps = fork ? c->s2 : c->s;
+  hipStream_t ps = fork ? c->s2 : ms;
   if (c->has_pair) {
     if (fork) {
-      HIPCHK(hipEventRecord(c->ev_fork, c->s));
+      HIPCHK(hipEventRecord(c->ev_fork, ms));
       HIPCHK(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
     }
     RUN(K_PAIR, ps, launch_pair(d, w, est, c->pl.jsplit, ps));
     if (fork) HIPCHK(hipEventRecord(c->ev_join, c->s2));
   }
-  if (c->helpers > 0) {
-    c->epoch = c->epoch == 0x7fffffff ? 1 : c->epoch + 1;
-    const int ep = c->epoch;
-    RUN(K_RECURSION, c->s, launch_recursion_coop(d, w, c->helpers, ep, c->s));
-  } else {
-    RUN(K_RECURSION, c->s, launch_recursion(d, w, c->s));
-  }
-  RUN(K_REDUCE, c->s, launch_probs_reduce(d, w, c->s));
-  if (fork) HIPCHK(hipStreamWaitEvent(c->s, c->ev_join, 0));
+  if (c->helpers > 0) RUN(K_RECURSION, ms, launch_recursion_coop(d, w, c->helpers, ms));
+  else RUN(K_RECURSION, ms, launch_recursion(d, w, ms));
+  RUN(K_REDUCE, ms, launch_probs_reduce(d, w, ms));
+  if (fork) HIPCHK(hipStreamWaitEvent(ms, c->ev_join, 0));
   return PIMD_OK;
+}
+
+// Captures one steady MD step (evaluation, then the fused second half of this step and first
+// half of the next) into c->gexec.  On any failure the graph stays absent and graph_state = 3.
+void build_step_graph(pimd_ctx* c) {
+  hipGraph_t g = nullptr;
+  pimd_status st = PIMD_ERR_DEVICE;
+  hipError_t e = hipStreamBeginCapture(c->sc, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = evaluate(c, false, c->sc);
+    if (st == PIMD_OK) {
+      e = launch_integrate_fused(c->pl.d, c->w, c->sc);
+      if (e != hipSuccess) st = PIMD_ERR_DEVICE;
+    }
+    const hipError_t e2 = hipStreamEndCapture(c->sc, &g);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess && st == PIMD_OK && g != nullptr) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  if (g != nullptr) (void)hipGraphDestroy(g);
+  if (e != hipSuccess || st != PIMD_OK || c->gexec == nullptr) {
+    c->gexec = nullptr;
+    c->graph_state = 3;
+    (void)hipGetLastError();
+  } else {
+    c->graph_state = 1;
+  }
 }
 
 pimd_status sample(pimd_ctx* c, bool record) {
@@ -373,8 +397,10 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   w.intwork = (int4*)(c->ws + off[S_INTW]);
   w.dbg = (double*)(c->ws + off[S_DBG]);
   for (auto& r : c->pl.reps) c->has_pair = c->has_pair || r.amp > 0;
+  c->graph_state = (cfg->flags & PIMD_FLAG_GRAPH) ? 0 : 2;
   auto cleanup = [&](pimd_status s2) {
     if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->sc) (void)hipStreamDestroy(c->sc);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
@@ -390,6 +416,7 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
     e = hipMemcpyAsync(w.intwork, c->pl.intwork.data(), sizeof(int4) * c->pl.intwork.size(), hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) return cleanup(fail(PIMD_ERR_DEVICE, std::string("pimd_create: ") + hipGetErrorString(e)));
@@ -424,7 +451,9 @@ pimd_status pimd_destroy(pimd_ctx* c) {
   if (c->s2) (void)hipStreamSynchronize(c->s2);
   for (auto& pr : c->prof) { (void)hipEventDestroy(pr.second.first); (void)hipEventDestroy(pr.second.second); }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->s2) (void)hipStreamDestroy(c->s2);
+  if (c->sc) (void)hipStreamDestroy(c->sc);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   delete c;
@@ -477,7 +506,7 @@ pimd_status pimd_get_state(pimd_ctx* c, int32_t r, double* x, double* p, double*
 
 pimd_status pimd_compute_forces(pimd_ctx* c) {
   if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
-  pimd_status st = evaluate(c, true);
+  pimd_status st = evaluate(c, true, c->s);
   if (st != PIMD_OK) return st;
   RUN(K_INT2, c->s, launch_integrate_second(c->pl.d, c->w, false, c->s));
   st = sample(c, false);
@@ -505,20 +534,31 @@ pimd_status pimd_step(pimd_ctx* c, int64_t n_steps, int32_t sample_every) {
   const Dims& d = c->pl.d;
   pimd_status st;
   if (!c->forces_valid && n_steps > 0) {
-    if ((st = evaluate(c, false)) != PIMD_OK) return st;
+    if ((st = evaluate(c, false, c->s)) != PIMD_OK) return st;
     RUN(K_INT2, c->s, launch_integrate_second(d, c->w, false, c->s));
     c->forces_valid = true;
   }
   // Step k: [first half] evaluate [second half].  The second half of step k and the first
   // half of step k+1 run as one fused pass unless step k is sampled (the estimators need the
   // state between the halves) or k is the last step of this call.
+  // A steady step (first half already fused into the previous step, not sampled, not last) is
+  // replayed from the captured step graph when one is available.
   bool pending_first = true;
   for (int64_t it = 0; it < n_steps; ++it) {
     const bool smp = sample_every > 0 && ((c->step + 1) % sample_every == 0);
-    if (pending_first) RUN(K_INT1, c->s, launch_integrate_first(d, c->w, c->s));
-    if ((st = evaluate(c, smp)) != PIMD_OK) return st;
-    c->step += 1;
     const bool last = (it + 1 == n_steps);
+    if (!pending_first && !smp && !last && !c->profiling && (c->graph_state == 0 || c->graph_state == 1)) {
+      if (c->graph_state == 0) build_step_graph(c);
+      if (c->gexec != nullptr) {
+        HIPCHK(hipGraphLaunch(c->gexec, c->s));
+        c->step += 1;
+        c->graph_replays += 1;
+        continue;
+      }
+    }
+    if (pending_first) RUN(K_INT1, c->s, launch_integrate_first(d, c->w, c->s));
+    if ((st = evaluate(c, smp, c->s)) != PIMD_OK) return st;
+    c->step += 1;
     if (smp || last) {
       RUN(K_INT2, c->s, launch_integrate_second(d, c->w, true, c->s));
       if (smp) {
@@ -668,6 +708,13 @@ const char* pimd_kernel_name(int32_t kind) {
 pimd_status pimd_synchronize(pimd_ctx* c) {
   if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
   HIPCHK(hipStreamSynchronize(c->s));
+  return PIMD_OK;
+}
+
+pimd_status pimd_graph_info(pimd_ctx* c, int32_t* state, int64_t* replays) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  if (state) *state = c->graph_state;
+  if (replays) *replays = c->graph_replays;
   return PIMD_OK;
 }
 

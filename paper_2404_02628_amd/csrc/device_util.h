@@ -47,6 +47,16 @@ __device__ inline double read_lane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// Work item of workgroup b in a launch of n workgroups.  Workgroups are dealt round-robin over
+// the kXcds accelerator dies (b runs on die b mod kXcds, each die with its own L2); this gives
+// each die one contiguous range of work items, so items listed next to each other (the tiles of
+// one slice) read their shared inputs through one L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_work_index(int b, int n) {
+  const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
+  return x * q + min(x, r) + k;
+}
+
 // log of xi^k with 0^0 = 1; lnxi = log(xi) (-inf for xi = 0), k >= 0.
 __device__ inline double xi_pow_log(int k, double lnxi) { return k == 0 ? 0.0 : (double)k * lnxi; }
 

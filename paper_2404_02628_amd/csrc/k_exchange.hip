@@ -49,31 +49,33 @@ template <int D>
 struct RecMap {
   const double* a; const double* b; const double* lk;
   int N, npp, dir;
-  double blink;  // beta
-  __device__ inline void row(int i, double (&pt)[D], double& rho) const {
-    // valid for 1 <= i <= N
+  double beta;
+  // end point p_i and the link value entering rho_i, for 1 <= i <= N
+  __device__ inline void row_load(int i, double (&pt)[D], double& lv) const {
     if (dir == 0) {
 #pragma unroll
       for (int c = 0; c < D; ++c) pt[c] = b[(long long)c * npp + (i - 1)];
-      rho = blink * lk[i - 1] - log((double)i);
+      lv = lk[i - 1];
     } else {
 #pragma unroll
       for (int c = 0; c < D; ++c) pt[c] = a[(long long)c * npp + (N - i)];
-      rho = (i < N) ? blink * lk[N - i - 1] : 0.0;
+      lv = (i < N) ? lk[N - i - 1] : 0.0;
     }
   }
-  __device__ inline void col(int j, double (&pt)[D], double& gam) const {
-    // valid for 0 <= j <= N-1
+  __device__ inline double row_rho(int i, double lv) const {
+    return dir == 0 ? beta * lv - log((double)i) : beta * lv;
+  }
+  // column point q_j, for 0 <= j <= N-1
+  __device__ inline void col_load(int j, double (&q)[D]) const {
     if (dir == 0) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) pt[c] = a[(long long)c * npp + j];
-      gam = 0.0;
+      for (int c = 0; c < D; ++c) q[c] = a[(long long)c * npp + j];
     } else {
 #pragma unroll
-      for (int c = 0; c < D; ++c) pt[c] = b[(long long)c * npp + (N - j - 1)];
-      gam = -log((double)(N - j));
+      for (int c = 0; c < D; ++c) q[c] = b[(long long)c * npp + (N - j - 1)];
     }
   }
+  __device__ inline double col_gamma(int j) const { return dir == 0 ? 0.0 : -log((double)(N - j)); }
 };
 
 constexpr int kRecWaves = 8;
@@ -206,41 +208,182 @@ __device__ inline double max_term(const RowCtx& rc, const double (&pi)[D], const
 template <int D>
 struct RecShared {
   double tab[kExpTable];
-  double Am[kTile * kTile];   // column-major: Am[col * 64 + row]
+  double Am[kTile * kTile];             // in-block coefficients, column-major: Am[col * 64 + row]
   double pm[kRecWaves][kTile], ps[kRecWaves][kTile];
-  double pp[kRecWaves][D + 1][kTile];
-  double Dl[kTile], LBl[kTile], Wl[kTile];
-  double pbar[D + 1][kTile];
-  int flag;
+  double pp[kRecWaves][D + 1][kTile];   // per-wave sums over earlier columns: exp(pm) (ps, pp)
+  double qp[kRecWaves][D + 1][kTile];   // per-wave weighted payloads of the in-block columns
+  double Dl[kTile], Wl[kTile];          // row scales D_i and scaled unknowns w_i of the block
+  double4 col[2][kTile];                // column records {q_j, gamma_j (+ G_j once solved)}: this block, previous
 };
 
-// Steps (2)-(5) for one block of 64 rows, given each wave's partial sums over the earlier
-// columns in pm/ps/pp (log-sum-exp form: exp(m) (s, P)).  Writes G_i, adds G_i to the column
-// records, optionally publishes the block (release store of `epoch`), and writes the weighted
-// row averages.
+// What wave 0 keeps in registers from a block's solve until it writes the block's row averages
+// (at the start of the next block, or after the last one).
 template <int D>
-__device__ inline void solve_block(RecShared<D>& sh, int blk, int N, const double (&pi)[D], double rho, bool valid,
-                                   double bc, double lnxi, double4* __restrict__ rec, double* __restrict__ G,
-                                   double* __restrict__ av, int npp, int* publish, int epoch) {
+struct RowCarry {
+  int i;
+  bool valid;
+  double w, bterm, pb[D + 1];
+};
+
+template <int D>
+__device__ inline void write_avg(const RecShared<D>& sh, const RowCarry<D>& cy, double* __restrict__ av,
+                                 long long npp) {
+  if (!cy.valid) return;
+  const int lane = threadIdx.x & 63;
+  const double inv = 1.0 / cy.w;
+#pragma unroll
+  for (int q = 0; q <= D; ++q) {
+    double v = cy.bterm * cy.pb[q];
+#pragma unroll
+    for (int w = 0; w < kRecWaves; ++w) v += sh.qp[w][q][lane];
+    av[(long long)q * npp + cy.i] = v * inv;
+  }
+}
+
+// (2a) in-block coefficients alpha_{i,j} (without G_j) from the staged column records; each wave
+// fills its eight columns.
+template <int D>
+__device__ inline void inblock_alpha(RecShared<D>& sh, int cur, int blk, int i, const double (&pi)[D], double rho,
+                                     bool valid, double bc, double lnxi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < kColsPerWave; ++u) {
+    const int sc = wave * kColsPerWave + u;
+    const int j = blk * kTile + sc;
+    const double4 r4 = sh.col[cur][sc];
+    const double qv[3] = {r4.x, r4.y, r4.z};
+    double d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) { const double t = pi[c] - qv[c]; d2 = fma(t, t, d2); }
+    const double v = xi_pow_log(i - 1 - j, lnxi) + rho + r4.w - bc * d2;
+    sh.Am[sc * kTile + lane] = (valid && j < i) ? v : -INFINITY;
+  }
+}
+
+
+// Max-plus pass D_i = max(LB_i, max_{s<i} (alpha_{i,s} + D_s)) with each lane's row of alpha held
+// in registers (alpha_{i,s} = -inf for s >= i).  Four rows per round: the in-group coefficients
+// come from the lanes that own those rows, and after the round's update `run` equals D on every
+// lane of the group, so at the end run_i = D_i.
+__device__ inline double maxplus_regs(const double* __restrict__ Am, double run) {
+  const int lane = threadIdx.x & 63;
+  double a[kTile];
+#pragma unroll
+  for (int s = 0; s < kTile; ++s) a[s] = Am[s * kTile + lane];
+#pragma unroll
+  for (int s0 = 0; s0 < kTile; s0 += 4) {
+    const double m10 = read_lane(a[s0], s0 + 1);
+    const double m20 = read_lane(a[s0], s0 + 2), m21 = read_lane(a[s0 + 1], s0 + 2);
+    const double m30 = read_lane(a[s0], s0 + 3), m31 = read_lane(a[s0 + 1], s0 + 3);
+    const double m32 = read_lane(a[s0 + 2], s0 + 3);
+    const double d0 = read_lane(run, s0);
+    const double d1 = fmax(read_lane(run, s0 + 1), m10 + d0);
+    const double d2 = fmax(fmax(read_lane(run, s0 + 2), m20 + d0), m21 + d1);
+    const double d3 = fmax(fmax(fmax(read_lane(run, s0 + 3), m30 + d0), m31 + d1), m32 + d2);
+    run = fmax(fmax(run, a[s0] + d0), a[s0 + 1] + d1);
+    run = fmax(fmax(run, a[s0 + 2] + d2), a[s0 + 3] + d3);
+  }
+  return run;
+}
+
+// Forward substitution w_i = acc_i + sum_{s<i} c_{i,s} w_s with each lane's row of c held in
+// registers (c_{i,s} = 0 for s >= i).  Four rows per round: their in-group coefficients come
+// from the lanes that own those rows, and after the round's update acc equals w on every lane
+// of the group, so at the end acc_i = w_i.
+__device__ inline double substitute_regs(const double* __restrict__ Am, double acc) {
+  const int lane = threadIdx.x & 63;
+  double c[kTile];
+#pragma unroll
+  for (int s = 0; s < kTile; ++s) c[s] = Am[s * kTile + lane];
+#pragma unroll
+  for (int s0 = 0; s0 < kTile; s0 += 4) {
+    const double m10 = read_lane(c[s0], s0 + 1);
+    const double m20 = read_lane(c[s0], s0 + 2), m21 = read_lane(c[s0 + 1], s0 + 2);
+    const double m30 = read_lane(c[s0], s0 + 3), m31 = read_lane(c[s0 + 1], s0 + 3);
+    const double m32 = read_lane(c[s0 + 2], s0 + 3);
+    const double w0 = read_lane(acc, s0);
+    const double w1 = fma(m10, w0, read_lane(acc, s0 + 1));
+    const double w2 = fma(m21, w1, fma(m20, w0, read_lane(acc, s0 + 2)));
+    const double w3 = fma(m32, w2, fma(m31, w1, fma(m30, w0, read_lane(acc, s0 + 3))));
+    acc = fma(c[s0], w0, acc);
+    acc = fma(c[s0 + 1], w1, acc);
+    acc = fma(c[s0 + 2], w2, acc);
+    acc = fma(c[s0 + 3], w3, acc);
+  }
+  return acc;
+}
+
+// (3) scaled coefficients c_{i,s} = exp(alpha_{i,s} + D_s - D_i) of the strictly lower triangle,
+// 63 entries per lane-row of work: pass k of wave w takes column s = 4w + k for rows s+1..63 and
+// column 63-s for rows 64-s..63.  Each wave also zeroes the upper triangle of its own eight
+// columns (the substitution reads whole rows).
+template <int D>
+__device__ inline void scaled_coefficients(RecShared<D>& sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < kColsPerWave; ++u) {
+    const int sc = wave * kColsPerWave + u;
+    if (lane <= sc) sh.Am[sc * kTile + lane] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kTile / 2 / kRecWaves; ++k) {
+    const int s = wave * (kTile / 2 / kRecWaves) + k;   // 0..31
+    const bool lower = lane > s;
+    const int col = lower ? s : kTile - 1 - s;
+    const int row = lower ? lane : kTile - s + lane;     // lanes 0..s-1 -> rows 64-s..63
+    if (lower || lane < s) {
+      const int idx = col * kTile + row;
+      sh.Am[idx] = fast_exp(sh.Am[idx] + sh.Dl[col] - sh.Dl[row], sh.tab);
+    }
+  }
+}
+
+// G_i, the completed column record of row i (LDS and global), the next block's column records,
+// the publish store and the carried row data; wave 0 only.
+template <int D>
+__device__ inline void finish_rows(RecShared<D>& sh, int blk, int cur, int N, bool valid, double Di, double wi,
+                                   double bterm, double4* __restrict__ rec, double* __restrict__ G,
+                                   const double4& col_next, int* publish, int epoch, RowCarry<D>& cy) {
+  const int lane = threadIdx.x & 63;
+  const int i = blk * kTile + lane;
+  sh.Wl[lane] = wi;
+  if (i <= N) {
+    const double Gi = Di + log(wi);
+    G[i] = Gi;
+    if (i < N) {
+      double4 r4 = sh.col[cur][lane];
+      r4.w += Gi;
+      sh.col[cur][lane] = r4;
+      rec[i] = r4;
+    }
+  }
+  sh.col[cur ^ 1][lane] = col_next;
+  if (publish != nullptr && lane == 0) __hip_atomic_store(publish, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  cy.i = i;
+  cy.valid = valid;
+  cy.w = wi;
+  cy.bterm = bterm;
+}
+
+// Steps (2)-(5) of one block of 64 rows, entered once every wave has stored its partial sums
+// over the earlier columns (pm/ps/pp, log-sum-exp form exp(m) (s, P)) and its in-block
+// coefficients alpha (Am).  Wave 0 writes the previous block's row averages, combines the
+// partials into LB_i and runs the max-plus pass for the row scales D_i (every scaled coefficient
+// <= 1, so 1 <= w_i <= 2^64); all waves form the scaled coefficients; wave 0 solves for w_i,
+// writes G_i, completes the column records (LDS and global), stages the next block's records and
+// publishes the block (release store of `epoch`, when `publish` is set).  All waves then form
+// the in-block weighted payloads (qp).  Wave 1 runs `idle` while wave 0 combines and scales.
+template <int D, class Idle>
+__device__ inline void solve_block(RecShared<D>& sh, int blk, int cur, int N, bool valid, double4* __restrict__ rec,
+                                   double* __restrict__ G, double* __restrict__ av, long long npp,
+                                   const double (&pi)[D], const double4& col_next, int* publish, int epoch,
+                                   RowCarry<D>& cy, Idle&& idle) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blk * kTile + lane;
-  // (2a) in-block coefficients alpha_{i,j} (without G_j), j = blk*64 + sc, column-major
-  for (int sc = wave * kColsPerWave; sc < (wave + 1) * kColsPerWave; ++sc) {
-    const int j = blk * kTile + sc;
-    double v = -INFINITY;
-    if (valid && j < i) {
-      const double4 r4 = rec[j];
-      const double qv[3] = {r4.x, r4.y, r4.z};
-      double d2 = 0.0;
-#pragma unroll
-      for (int c = 0; c < D; ++c) { const double t = pi[c] - qv[c]; d2 = fma(t, t, d2); }
-      v = xi_pow_log(i - 1 - j, lnxi) + rho + r4.w - bc * d2;
-    }
-    sh.Am[sc * kTile + lane] = v;
-  }
   __syncthreads();
-
+  double LB = 0.0;
   if (wave == 0) {
+    if (blk > 0) write_avg<D>(sh, cy, av, npp);
     double M = sh.pm[0][lane];
 #pragma unroll
     for (int w = 1; w < kRecWaves; ++w) M = fmax(M, sh.pm[w][lane]);
@@ -249,144 +392,68 @@ __device__ inline void solve_block(RecShared<D>& sh, int blk, int N, const doubl
     for (int q = 0; q <= D; ++q) PS[q] = 0.0;
 #pragma unroll
     for (int w = 0; w < kRecWaves; ++w) {
-      const double f = sh.ps[w][lane] > 0.0 ? exp(sh.pm[w][lane] - M) : 0.0;
+      const double f = sh.ps[w][lane] > 0.0 ? fast_exp(sh.pm[w][lane] - M, sh.tab) : 0.0;
       S = fma(sh.ps[w][lane], f, S);
 #pragma unroll
       for (int q = 0; q <= D; ++q) PS[q] = fma(sh.pp[w][q][lane], f, PS[q]);
     }
-    double LB = (S > 0.0) ? M + log(S) : -INFINITY;
+    LB = (S > 0.0) ? M + log(S) : -INFINITY;
+    const double invS = S > 0.0 ? 1.0 / S : 0.0;
 #pragma unroll
-    for (int q = 0; q <= D; ++q) sh.pbar[q][lane] = S > 0.0 ? PS[q] / S : 0.0;
+    for (int q = 0; q <= D; ++q) cy.pb[q] = PS[q] * invS;
     if (i == 0) LB = 0.0;            // seed row: G_0 = 0
     if (!valid && i != 0) LB = 0.0;  // padding rows stay finite and unused
-    sh.LBl[lane] = LB;
-    // (2b) max-plus scales D_i = max(LB_i, max_{s<lane}(alpha_{i,s} + D_s)), four rows per round:
-    // the four rows of a group are finished from broadcast values, then the rest updated.
-    double run = LB, mine = 0.0;
-    for (int s0 = 0; s0 < kTile; s0 += 4) {
-      const double r0 = read_lane(run, s0), r1 = read_lane(run, s0 + 1);
-      const double r2 = read_lane(run, s0 + 2), r3 = read_lane(run, s0 + 3);
-      const double a10 = sh.Am[s0 * kTile + s0 + 1];
-      const double a20 = sh.Am[s0 * kTile + s0 + 2], a21 = sh.Am[(s0 + 1) * kTile + s0 + 2];
-      const double a30 = sh.Am[s0 * kTile + s0 + 3], a31 = sh.Am[(s0 + 1) * kTile + s0 + 3];
-      const double a32 = sh.Am[(s0 + 2) * kTile + s0 + 3];
-      const double D0 = r0;
-      const double D1 = fmax(r1, a10 + D0);
-      const double D2 = fmax(r2, fmax(a20 + D0, a21 + D1));
-      const double D3 = fmax(r3, fmax(fmax(a30 + D0, a31 + D1), a32 + D2));
-      const int g = lane - s0;
-      if (g == 0) mine = D0;
-      if (g == 1) mine = D1;
-      if (g == 2) mine = D2;
-      if (g == 3) mine = D3;
-      if (g > 3) {
-        const double u0 = sh.Am[s0 * kTile + lane] + D0, u1 = sh.Am[(s0 + 1) * kTile + lane] + D1;
-        const double u2 = sh.Am[(s0 + 2) * kTile + lane] + D2, u3 = sh.Am[(s0 + 3) * kTile + lane] + D3;
-        run = fmax(fmax(run, fmax(u0, u1)), fmax(u2, u3));
-      }
-    }
-    sh.Dl[lane] = mine;
+    sh.Dl[lane] = maxplus_regs(sh.Am, LB);
+  } else if (wave == 1) {
+    idle();   // work for a wave that would otherwise wait for wave 0
   }
   __syncthreads();
-  // (3) scaled coefficients exp(alpha + D_s - D_i) <= 1
-  {
-    const double Di = sh.Dl[lane];
-    for (int sc = wave * kColsPerWave; sc < (wave + 1) * kColsPerWave; ++sc) {
-      const double v = sh.Am[sc * kTile + lane];
-      sh.Am[sc * kTile + lane] = (lane > sc) ? fast_exp(v + sh.Dl[sc] - Di, sh.tab) : 0.0;
-    }
-  }
+  scaled_coefficients<D>(sh);
   __syncthreads();
   if (wave == 0) {
-    // (4) forward substitution on w_i = exp(G_i - D_i), four rows per round
     const double Di = sh.Dl[lane];
-    double acc = fast_exp(sh.LBl[lane] - Di, sh.tab), mine = 1.0;
-    for (int s0 = 0; s0 < kTile; s0 += 4) {
-      const double c0 = read_lane(acc, s0), c1 = read_lane(acc, s0 + 1);
-      const double c2 = read_lane(acc, s0 + 2), c3 = read_lane(acc, s0 + 3);
-      const double m10 = sh.Am[s0 * kTile + s0 + 1];
-      const double m20 = sh.Am[s0 * kTile + s0 + 2], m21 = sh.Am[(s0 + 1) * kTile + s0 + 2];
-      const double m30 = sh.Am[s0 * kTile + s0 + 3], m31 = sh.Am[(s0 + 1) * kTile + s0 + 3];
-      const double m32 = sh.Am[(s0 + 2) * kTile + s0 + 3];
-      const double w0 = c0;
-      const double w1 = fma(m10, w0, c1);
-      const double w2 = fma(m21, w1, fma(m20, w0, c2));
-      const double w3 = fma(m32, w2, fma(m31, w1, fma(m30, w0, c3)));
-      const int g = lane - s0;
-      if (g == 0) mine = w0;
-      if (g == 1) mine = w1;
-      if (g == 2) mine = w2;
-      if (g == 3) mine = w3;
-      if (g > 3) {
-        acc = fma(sh.Am[s0 * kTile + lane], w0, acc);
-        acc = fma(sh.Am[(s0 + 1) * kTile + lane], w1, acc);
-        acc = fma(sh.Am[(s0 + 2) * kTile + lane], w2, acc);
-        acc = fma(sh.Am[(s0 + 3) * kTile + lane], w3, acc);
-      }
-    }
-    sh.Wl[lane] = mine;
-    if (i <= N) {
-      const double Gi = Di + log(mine);
-      G[i] = Gi;
-      if (i < N) rec[i].w += Gi;
-    }
+    const double bterm = fast_exp(LB - Di, sh.tab);
+    const double wi = substitute_regs(sh.Am, bterm);
+    finish_rows<D>(sh, blk, cur, N, valid, Di, wi, bterm, rec, G, col_next, publish, epoch, cy);
   }
   __syncthreads();
-  if (publish != nullptr && threadIdx.x == 0)
-    __hip_atomic_store(publish, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   // (5) weighted payloads of the in-block terms: the term of column s in row i is
-  // exp(D_i) * Am[s][i] * w_s; each wave sums its columns, wave 0 normalises by exp(G_i).
+  // exp(D_i) c_{i,s} w_s; each wave sums its columns (normalised by wave 0 later).
   {
     double Q[D + 1];
 #pragma unroll
     for (int q = 0; q <= D; ++q) Q[q] = 0.0;
-    for (int sc = wave * kColsPerWave; sc < (wave + 1) * kColsPerWave; ++sc) {
-      const int j = blk * kTile + sc;
-      if (valid && j < i) {
-        const double coef = sh.Am[sc * kTile + lane] * sh.Wl[sc];
-        const double4 r4 = rec[j];
-        const double qv[3] = {r4.x, r4.y, r4.z};
-        double d2 = 0.0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-          const double t = pi[c] - qv[c];
-          d2 = fma(t, t, d2);
-          Q[c] = fma(coef, qv[c], Q[c]);
-        }
-        Q[D] = fma(coef, d2, Q[D]);
+    for (int u = 0; u < kColsPerWave; ++u) {
+      const int sc = wave * kColsPerWave + u;
+      const double coef = sh.Am[sc * kTile + lane] * sh.Wl[sc];
+      const double4 r4 = sh.col[cur][sc];
+      const double qv[3] = {r4.x, r4.y, r4.z};
+      double d2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double t = pi[c] - qv[c];
+        d2 = fma(t, t, d2);
+        Q[c] = fma(coef, qv[c], Q[c]);
       }
+      Q[D] = fma(coef, d2, Q[D]);
     }
 #pragma unroll
-    for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = Q[q];
+    for (int q = 0; q <= D; ++q) sh.qp[wave][q][lane] = Q[q];
   }
-  __syncthreads();
-  if (wave == 0 && valid) {
-    const double wi = sh.Wl[lane];
-    const double bterm = fast_exp(sh.LBl[lane] - sh.Dl[lane], sh.tab);   // the earlier-column term of row i
-#pragma unroll
-    for (int q = 0; q <= D; ++q) {
-      double v = bterm * sh.pbar[q][lane];
-#pragma unroll
-      for (int w = 0; w < kRecWaves; ++w) v += sh.pp[w][q][lane];
-      av[(long long)q * npp + i] = v / wi;
-    }
-  }
-  __syncthreads();
 }
 
-// Fills the column records {q_j, gamma_j} (G_j is added once row j is solved).
+// Column record {q_j, gamma_j} of column j (zeros past the last column).
 template <int D>
-__device__ inline void init_columns(const RecMap<D>& mp, double4* __restrict__ rec, int N) {
-  for (int j = threadIdx.x; j < N; j += blockDim.x) {
-    double q[D], gam;
-    mp.col(j, q, gam);
-    double4 r4;
+__device__ inline double4 make_col(const RecMap<D>& mp, int j, const double (&q)[D]) {
+  double4 r4 = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (j < mp.N) {
     r4.x = q[0];
-    r4.y = D > 1 ? q[D > 1 ? 1 : 0] : 0.0;
-    r4.z = D > 2 ? q[D > 2 ? 2 : 0] : 0.0;
-    r4.w = gam;
-    rec[j] = r4;
+    if (D > 1) r4.y = q[D > 1 ? 1 : 0];
+    if (D > 2) r4.z = q[D > 2 ? 2 : 0];
+    r4.w = mp.col_gamma(j);
   }
+  return r4;
 }
 
 template <int D>
@@ -395,11 +462,27 @@ __device__ inline RecMap<D> rec_map(const RepDev& R, const double* ends, const d
   mp.a = ends + 2LL * D * R.part;
   mp.b = mp.a + (long long)D * R.npp;
   mp.lk = link + R.part;
-  mp.N = R.n; mp.npp = R.npp; mp.dir = dir; mp.blink = R.beta;
+  mp.N = R.n; mp.npp = R.npp; mp.dir = dir; mp.beta = R.beta;
   return mp;
 }
 
 __device__ inline int xi_mode(double xi) { return xi == 1.0 ? kXiOne : (xi == 0.0 ? kXiZero : kXiGen); }
+
+// Register-prefetched inputs of the next block: end points and link values of its rows (all
+// waves), raw column points of its columns (wave 0).
+template <int D>
+struct Prefetch {
+  double p[D], lv, q[D];
+  __device__ inline void load(const RecMap<D>& mp, int blk, bool wave0) {
+    const int lane = threadIdx.x & 63;
+    const int i = blk * kTile + lane;
+#pragma unroll
+    for (int c = 0; c < D; ++c) { p[c] = 0.0; q[c] = 0.0; }
+    lv = 0.0;
+    if (i >= 1 && i <= mp.N) mp.row_load(i, p, lv);
+    if (wave0 && i < mp.N) mp.col_load(i, q);
+  }
+};
 
 // One workgroup per replica and direction (batched replicas fill the machine).
 template <int D>
@@ -421,18 +504,24 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restr
   const int xm = xi_mode(R.xi);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (N + 1 + kTile - 1) / kTile;   // rows 0..N
+  const long long npp = R.npp;
 
   if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
-  init_columns<D>(mp, rec, N);
+  Prefetch<D> pf;
+  pf.load(mp, 0, wave == 0);
+  if (wave == 0) sh.col[0][lane] = make_col<D>(mp, lane, pf.q);
+  RowCarry<D> cy{};
   __syncthreads();
 
   for (int blk = 0; blk < nblk; ++blk) {
+    const int cur = blk & 1;
     const int i = blk * kTile + lane;
     const bool valid = (i >= 1 && i <= N);
-    double pi[D], rho = 0.0;
+    double pi[D];
 #pragma unroll
-    for (int c = 0; c < D; ++c) pi[c] = 0.0;
-    if (valid) mp.row(i, pi, rho);
+    for (int c = 0; c < D; ++c) pi[c] = pf.p[c];
+    const double rho = valid ? mp.row_rho(i, pf.lv) : 0.0;
+    if (blk + 1 < nblk) pf.load(mp, blk + 1, wave == 0);
     const RowCtx rc{i, rho, bc, lnxi};
     const int jend = blk * kTile;
 
@@ -441,10 +530,19 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restr
     if (jend > 0) {
       double mx = -INFINITY;
       if (valid) {
-        const int j0 = jend - kTile + wave * kColsPerWave;
-        if (xm == kXiOne) mx = max_term<D, kXiOne>(rc, pi, rec, j0, kColsPerWave);
-        else if (xm == kXiZero) mx = max_term<D, kXiZero>(rc, pi, rec, j0, kColsPerWave);
-        else mx = max_term<D, kXiGen>(rc, pi, rec, j0, kColsPerWave);
+        const double4* cp = sh.col[cur ^ 1];
+        const int j0 = wave * kColsPerWave;
+#pragma unroll
+        for (int u = 0; u < kColsPerWave; ++u) {
+          double d2;
+          const double4 r4 = cp[j0 + u];
+          const int j = jend - kTile + j0 + u;
+          double t;
+          if (xm == kXiOne) t = term_of<D, kXiOne>(rc, pi, r4, j, d2);
+          else if (xm == kXiZero) t = term_of<D, kXiZero>(rc, pi, r4, j, d2);
+          else t = term_of<D, kXiGen>(rc, pi, r4, j, d2);
+          mx = fmax(mx, t);
+        }
       }
       sh.pm[wave][lane] = mx;
       __syncthreads();
@@ -470,8 +568,12 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restr
     sh.ps[wave][lane] = s;
 #pragma unroll
     for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = P[q];
-    solve_block<D>(sh, blk, N, pi, rho, valid, bc, lnxi, rec, G, av, R.npp, nullptr, 0);
+    inblock_alpha<D>(sh, cur, blk, i, pi, rho, valid, bc, lnxi);
+    const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
+    solve_block<D>(sh, blk, cur, N, valid, rec, G, av, npp, pi, cn, nullptr, 0, cy, [] {});
   }
+  __syncthreads();
+  if (wave == 0) write_avg<D>(sh, cy, av, npp);
 }
 
 // ------------------------------------------------------- cooperative schedule (one large replica)
@@ -479,10 +581,10 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restr
 // One chain workgroup per replica and direction runs the blocks in order; H helper workgroups
 // per chain add up, for future row blocks, the contributions of every column panel the chain has
 // already finished (panel c = the columns of block c), so the chain itself only adds the panel
-// it has just produced.  Helper h owns row blocks 2+h, 2+h+H, ...; for its block b it folds in
-// panels 0..b-2 as they are published and then publishes the partial sums of block b.  Flags
-// hold the epoch of the launch that set them, so they never need clearing.  All workgroups are
-// launched cooperatively (co-resident), every wait depends only on work earlier in the chain,
+// it has just produced (from LDS).  Helper h owns row blocks 2+h, 2+h+H, ...; for its block b it
+// folds in panels 0..b-2 as they are published and then publishes the partial sums of block b.
+// Flags hold the epoch of the launch that set them, so they never need clearing.  All workgroups
+// are launched cooperatively (co-resident), every wait depends only on work earlier in the chain,
 // and every wait gives up after a bounded number of polls (raising an error word) instead of
 // hanging.
 
@@ -504,15 +606,16 @@ __device__ inline bool wait_epoch(const int* flag, int epoch, int* err) {
 }
 
 // Folds columns [j0, j0 + n) into the running log-sum-exp (m, s, P): one rescale per slice.
+// `recs` points at the record of column j0 (global or LDS).
 template <int D, int XM>
-__device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const double4* __restrict__ rec, int j0,
-                                  int n, const double* tab, double& m, double& s, double (&P)[D + 1]) {
+__device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const double4* recs, int j0, int n,
+                                  const double* tab, double& m, double& s, double (&P)[D + 1]) {
   double t[kColsPerWave], d2[kColsPerWave];
   double4 r[kColsPerWave];
   double mt = -INFINITY;
 #pragma unroll
   for (int u = 0; u < kColsPerWave; ++u) {
-    r[u] = rec[j0 + min(u, n - 1)];
+    r[u] = recs[min(u, n - 1)];
     t[u] = term_of<D, XM>(rc, pi, r[u], j0 + u, d2[u]);
     if (u >= n) t[u] = -INFINITY;
     mt = fmax(mt, t[u]);
@@ -535,11 +638,11 @@ __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const
 }
 
 template <int D>
-__device__ inline void fold_any(int xm, const RowCtx& rc, const double (&pi)[D], const double4* rec, int j0, int n,
+__device__ inline void fold_any(int xm, const RowCtx& rc, const double (&pi)[D], const double4* recs, int j0, int n,
                                 const double* tab, double& m, double& s, double (&P)[D + 1]) {
-  if (xm == kXiOne) slice_fold<D, kXiOne>(rc, pi, rec, j0, n, tab, m, s, P);
-  else if (xm == kXiZero) slice_fold<D, kXiZero>(rc, pi, rec, j0, n, tab, m, s, P);
-  else slice_fold<D, kXiGen>(rc, pi, rec, j0, n, tab, m, s, P);
+  if (xm == kXiOne) slice_fold<D, kXiOne>(rc, pi, recs, j0, n, tab, m, s, P);
+  else if (xm == kXiZero) slice_fold<D, kXiZero>(rc, pi, recs, j0, n, tab, m, s, P);
+  else slice_fold<D, kXiGen>(rc, pi, recs, j0, n, tab, m, s, P);
 }
 
 template <int D>
@@ -550,8 +653,9 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
                                                                 double4* __restrict__ colrec,
                                                                 double* __restrict__ avg, int* __restrict__ flags,
                                                                 double* __restrict__ partial, int* __restrict__ err,
-                                                                int nchains, int H, int epoch) {
+                                                                int nchains, int H) {
   __shared__ RecShared<D> sh;
+  const int epoch = err[1];   // stamp of this evaluation (advanced by the spring kernel)
   const bool is_chain = (int)blockIdx.x < nchains;
   const int chain = is_chain ? (int)blockIdx.x : ((int)blockIdx.x - nchains) % nchains;
   const int h = is_chain ? -1 : ((int)blockIdx.x - nchains) / nchains;
@@ -573,56 +677,83 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
   if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
 
   if (is_chain) {
-    init_columns<D>(mp, rec, N);
+    Prefetch<D> pf;
+    pf.load(mp, 0, wave == 0);
+    if (wave == 0) sh.col[0][lane] = make_col<D>(mp, lane, pf.q);
+    RowCarry<D> cy{};
+    // wave 1 holds the helper's partial sums over panels 0..blk-2 for the rows of block blk; it
+    // fetches them during the previous block, while wave 0 combines and scales
+    bool have_part = false;
+    double hm = -1e300, hs = 0.0, hP[D + 1];
+#pragma unroll
+    for (int q = 0; q <= D; ++q) hP[q] = 0.0;
     __syncthreads();
     for (int blk = 0; blk < nblk; ++blk) {
+      const int cur = blk & 1;
       const int i = blk * kTile + lane;
       const bool valid = (i >= 1 && i <= N);
-      double pi[D], rho = 0.0;
+      double pi[D];
 #pragma unroll
-      for (int c = 0; c < D; ++c) pi[c] = 0.0;
-      if (valid) mp.row(i, pi, rho);
+      for (int c = 0; c < D; ++c) pi[c] = pf.p[c];
+      const double rho = valid ? mp.row_rho(i, pf.lv) : 0.0;
+      if (blk + 1 < nblk) pf.load(mp, blk + 1, wave == 0);
       const RowCtx rc{i, rho, bc, lnxi};
+      inblock_alpha<D>(sh, cur, blk, i, pi, rho, valid, bc, lnxi);
       double m = -1e300, s = 0.0, P[D + 1];
 #pragma unroll
       for (int q = 0; q <= D; ++q) P[q] = 0.0;
-      // the panel just finished (columns of block blk-1), one 8-column slice per wave
-      if (blk >= 1 && valid) fold_any<D>(xm, rc, pi, rec, (blk - 1) * kTile + wave * kColsPerWave, kColsPerWave,
-                                         sh.tab, m, s, P);
-      // panels 0..blk-2 from the helper that owns this block
-      if (blk >= 2) {
-        if (threadIdx.x == 0) sh.flag = wait_epoch(part_ready + blk, epoch, err) ? 1 : 0;
-        __syncthreads();
-        if (wave == 0 && valid && sh.flag) {
-          const double mh = pt[i], shs = pt[npp + i];
-          if (shs > 0.0) {
-            const double M = fmax(m, mh);
-            const double f0 = exp(m - M), f1 = exp(mh - M);
-            s = s * f0 + shs * f1;
+      // the panel just finished (columns of block blk-1, in LDS), one 8-column slice per wave
+      if (blk >= 1 && valid)
+        fold_any<D>(xm, rc, pi, sh.col[cur ^ 1] + wave * kColsPerWave, (blk - 1) * kTile + wave * kColsPerWave,
+                    kColsPerWave, sh.tab, m, s, P);
+      if (have_part && hs > 0.0) {
+        const double M = fmax(m, hm);
+        const double f0 = fast_exp(m - M, sh.tab), f1 = fast_exp(hm - M, sh.tab);
+        s = s * f0 + hs * f1;
 #pragma unroll
-            for (int q = 0; q <= D; ++q) P[q] = P[q] * f0 + pt[(2 + q) * npp + i] * f1;
-            m = M;
-          }
-        }
+        for (int q = 0; q <= D; ++q) P[q] = P[q] * f0 + hP[q] * f1;
+        m = M;
       }
       sh.pm[wave][lane] = m;
       sh.ps[wave][lane] = s;
 #pragma unroll
       for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = P[q];
-      solve_block<D>(sh, blk, N, pi, rho, valid, bc, lnxi, rec, G, av, R.npp, panel_ready + blk, epoch);
+      const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
+      const int nb = blk + 1;
+      auto fetch_next = [&] {
+        have_part = false;
+        if (nb >= 2 && nb < nblk) {
+          int ok = 1;
+          if (lane == 0) ok = wait_epoch(part_ready + nb, epoch, err) ? 1 : 0;
+          ok = __shfl(ok, 0, 64);
+          const int in = nb * kTile + lane;
+          if (ok && in <= N) {
+            have_part = true;
+            hm = pt[in];
+            hs = pt[npp + in];
+#pragma unroll
+            for (int q = 0; q <= D; ++q) hP[q] = pt[(2 + q) * npp + in];
+          }
+        }
+      };
+      solve_block<D>(sh, blk, cur, N, valid, rec, G, av, npp, pi, cn, panel_ready + blk, epoch, cy, fetch_next);
     }
+    __syncthreads();
+    if (wave == 0) write_avg<D>(sh, cy, av, npp);
     return;
   }
 
   // helper h: row blocks 2+h, 2+h+H, ...
+  __syncthreads();
   int ready = -1;   // panels 0..ready are known to be published
   for (int blk = 2 + h; blk < nblk; blk += H) {
     const int i = blk * kTile + lane;
     const bool valid = (i >= 1 && i <= N);
-    double pi[D], rho = 0.0;
+    double pi[D], lv = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c) pi[c] = 0.0;
-    if (valid) mp.row(i, pi, rho);
+    if (valid) mp.row_load(i, pi, lv);
+    const double rho = valid ? mp.row_rho(i, lv) : 0.0;
     const RowCtx rc{i, rho, bc, lnxi};
     double m = -1e300, s = 0.0, P[D + 1];
 #pragma unroll
@@ -636,14 +767,17 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
             while (r + 1 <= blk - 2 &&
                    __hip_atomic_load(panel_ready + r + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch)
               ++r;
-          sh.flag = r;
+          sh.pm[0][0] = (double)r;
         }
         __syncthreads();
-        ready = sh.flag;
+        ready = (int)sh.pm[0][0];
         __syncthreads();
         if (ready < 0) return;   // a wait failed: the error word is raised, stop this helper
       }
-      if (valid) fold_any<D>(xm, rc, pi, rec, c * kTile + wave * kColsPerWave, kColsPerWave, sh.tab, m, s, P);
+      if (valid) {
+        const int j0 = c * kTile + wave * kColsPerWave;
+        fold_any<D>(xm, rc, pi, rec + j0, j0, kColsPerWave, sh.tab, m, s, P);
+      }
     }
     sh.pm[wave][lane] = m;
     sh.ps[wave][lane] = s;
@@ -659,7 +793,7 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
       for (int q = 0; q <= D; ++q) PS[q] = 0.0;
 #pragma unroll
       for (int w = 0; w < kRecWaves; ++w) {
-        const double f = sh.ps[w][lane] > 0.0 ? exp(sh.pm[w][lane] - M) : 0.0;
+        const double f = sh.ps[w][lane] > 0.0 ? fast_exp(sh.pm[w][lane] - M, sh.tab) : 0.0;
         S = fma(sh.ps[w][lane], f, S);
 #pragma unroll
         for (int q = 0; q <= D; ++q) PS[q] = fma(sh.pp[w][q][lane], f, PS[q]);
@@ -688,7 +822,7 @@ hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s) {
 }
 
 template <int D>
-static hipError_t launch_coop_d(const Dims& d, const DevPtrs& w, int H, int epoch, hipStream_t s) {
+static hipError_t launch_coop_d(const Dims& d, const DevPtrs& w, int H, hipStream_t s) {
   int nchains = 2 * d.R;
   dim3 grid((unsigned)(nchains * (1 + H))), block(kRecThreads);
   const RepDev* reps = w.reps;
@@ -702,15 +836,15 @@ static hipError_t launch_coop_d(const Dims& d, const DevPtrs& w, int H, int epoc
   double* partial = w.partial;
   int* err = w.err;
   void* args[] = {(void*)&reps, (void*)&ends, (void*)&link, (void*)&gf, (void*)&gb, (void*)&colrec, (void*)&avg,
-                  (void*)&flags, (void*)&partial, (void*)&err, (void*)&nchains, (void*)&H, (void*)&epoch};
+                  (void*)&flags, (void*)&partial, (void*)&err, (void*)&nchains, (void*)&H};
   return hipLaunchCooperativeKernel((const void*)k_recursion_coop<D>, grid, block, args, 0, s);
 }
 
-hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, int epoch, hipStream_t s) {
+hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, hipStream_t s) {
   switch (d.D) {
-    case 1: return launch_coop_d<1>(d, w, helpers, epoch, s);
-    case 2: return launch_coop_d<2>(d, w, helpers, epoch, s);
-    case 3: return launch_coop_d<3>(d, w, helpers, epoch, s);
+    case 1: return launch_coop_d<1>(d, w, helpers, s);
+    case 2: return launch_coop_d<2>(d, w, helpers, s);
+    case 3: return launch_coop_d<3>(d, w, helpers, s);
     default: return hipErrorInvalidValue;
   }
 }

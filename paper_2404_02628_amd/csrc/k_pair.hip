@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void k_pair_f32(const RepDev* __restrict__ rep
   constexpr int DP = D == 3 ? 4 : D;
   constexpr int IT = 4 / JS;          // 64-particle tiles per workgroup
   __shared__ double red[4][D + 2][64];
-  const int4 wk = work[blockIdx.x];
+  const int g = xcd_work_index((int)blockIdx.x, (int)gridDim.x);
+  const int4 wk = work[g];
   const RepDev& R = reps[wk.x];
   const int N = R.n, slice = wk.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -103,8 +104,8 @@ __global__ __launch_bounds__(256) void k_pair_f32(const RepDev* __restrict__ rep
     block_sum<2>(v, &red[0][0][0]);
     if (threadIdx.x == 0) {
       // u r'^2 = u r^2 log2(e)/s^2  ->  r^2/s^2 = r'^2 / log2(e)
-      pairpart[2LL * blockIdx.x + 0] = 0.5 * R.amp * v[0];
-      pairpart[2LL * blockIdx.x + 1] = 0.5 * R.amp * (v[0] - v[1] / 1.4426950408889634);
+      pairpart[2LL * g + 0] = 0.5 * R.amp * v[0];
+      pairpart[2LL * g + 1] = 0.5 * R.amp * (v[0] - v[1] / 1.4426950408889634);
     }
   }
 }
@@ -115,7 +116,8 @@ __global__ __launch_bounds__(256) void k_pair_f64(const RepDev* __restrict__ rep
                                                   double* __restrict__ pairpart, int P) {
   constexpr int IT = 4 / JS;
   __shared__ double red[4][D + 2][64];
-  const int4 wk = work[blockIdx.x];
+  const int g = xcd_work_index((int)blockIdx.x, (int)gridDim.x);
+  const int4 wk = work[g];
   const RepDev& R = reps[wk.x];
   const int N = R.n, slice = wk.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -176,8 +178,8 @@ __global__ __launch_bounds__(256) void k_pair_f64(const RepDev* __restrict__ rep
     double v[2] = {U, W};
     block_sum<2>(v, &red[0][0][0]);
     if (threadIdx.x == 0) {
-      pairpart[2LL * blockIdx.x + 0] = 0.5 * R.amp * v[0];
-      pairpart[2LL * blockIdx.x + 1] = 0.5 * R.amp * (v[0] - v[1]);
+      pairpart[2LL * g + 0] = 0.5 * R.amp * v[0];
+      pairpart[2LL * g + 1] = 0.5 * R.amp * (v[0] - v[1]);
     }
   }
 }

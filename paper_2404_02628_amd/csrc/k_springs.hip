@@ -11,6 +11,9 @@
 //     exp(-|r|^2/s^2) as one exp2.
 // End-bead exchange forces (Eqs. 15-16) are added later by the probability reduction.
 // Per-workgroup partial sums (E_int, links, trap energy) go to springpart in a fixed order.
+// Workgroup 0 also advances the launch stamp that the cooperative exchange recursion of the
+// same evaluation uses to mark its progress flags (a device counter, so that a replayed graph
+// of the step gets a new stamp each time).
 #include "pimd_internal.h"
 #include "device_util.h"
 
@@ -22,8 +25,13 @@ __global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restri
                                                           const double* __restrict__ x, double* __restrict__ f,
                                                           double* __restrict__ ends, double* __restrict__ link,
                                                           double* __restrict__ eint, float* __restrict__ xs,
-                                                          double* __restrict__ springpart, int P) {
+                                                          double* __restrict__ springpart, int* __restrict__ epoch,
+                                                          int P) {
   __shared__ double lds[3 * (kSpringBlock / 64)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int e = *epoch;
+    *epoch = (e <= 0 || e >= 0x7ffffffe) ? 1 : e + 1;
+  }
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
   const int N = R.n;
@@ -92,7 +100,7 @@ hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s) {
   dim3 grid((unsigned)d.nspringwg), block(kSpringBlock);
   const bool sh = d.precision == 1;
 #define L(DD, SH) hipLaunchKernelGGL((k_springs<DD, SH>), grid, block, 0, s, w.reps, w.springwork, w.x, w.f, \
-                                     w.ends, w.link, w.eint, w.xs, w.springpart, d.P)
+                                     w.ends, w.link, w.eint, w.xs, w.springpart, w.err + 1, d.P)
   switch (d.D * 2 + (sh ? 1 : 0)) {
     case 2: L(1, false); break;
     case 3: L(1, true); break;

@@ -88,7 +88,7 @@ __host__ __device__ inline int shadow_dp(int D) { return D == 3 ? 4 : D; }
 hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool estimators, int jsplit, hipStream_t s);
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s);
-hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, int epoch, hipStream_t s);
+hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, hipStream_t s);
 int recursion_coop_max_blocks_per_cu(int D);
 hipError_t launch_probs_reduce(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_integrate_first(const Dims& d, const DevPtrs& w, hipStream_t s);

@@ -23,12 +23,14 @@ LIB_PATH = os.path.join(_HERE, "libpimd.so")
 PIMD_OK, PIMD_ERR_INVALID, PIMD_ERR_DEVICE, PIMD_ERR_NONFINITE, PIMD_ERR_WORKSPACE, PIMD_ERR_STATE = 0, -1, -2, -3, -4, -5
 PIMD_FP64, PIMD_MIXED = 0, 1
 PIMD_HOST, PIMD_DEVICE = 0, 1
+PIMD_FLAG_GRAPH = 1
 
 EXPORTED = [
     "pimd_abi_version", "pimd_last_error", "pimd_workspace_bytes", "pimd_create", "pimd_destroy",
     "pimd_set_state", "pimd_get_state", "pimd_compute_forces", "pimd_get_forces", "pimd_step",
     "pimd_energies", "pimd_trace", "pimd_density", "pimd_reset_accumulators", "pimd_debug_potentials",
     "pimd_debug_probs", "pimd_profile", "pimd_kernel_times", "pimd_kernel_name", "pimd_synchronize",
+    "pimd_graph_info",
 ]
 
 
@@ -41,7 +43,7 @@ class pimd_replica(C.Structure):
 class pimd_config(C.Structure):
     _fields_ = [("n_replicas", C.c_int32), ("p", C.c_int32), ("dim", C.c_int32), ("precision", C.c_int32),
                 ("nhc_len", C.c_int32), ("sy_order", C.c_int32), ("density_bins", C.c_int32),
-                ("trace_capacity", C.c_int32), ("recursion_workgroups", C.c_int32), ("reserved", C.c_int32),
+                ("trace_capacity", C.c_int32), ("recursion_workgroups", C.c_int32), ("flags", C.c_int32),
                 ("density_rmax", C.c_double),
                 ("replicas", C.POINTER(pimd_replica))]
 
@@ -92,6 +94,7 @@ def load(path: str = LIB_PATH):
         "pimd_kernel_times": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]),
         "pimd_kernel_name": (C.c_char_p, [C.c_int32]),
         "pimd_synchronize": (C.c_int, [_vp]),
+        "pimd_graph_info": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -222,6 +225,13 @@ def pimd_synchronize(h):
     _chk(load().pimd_synchronize(h), "pimd_synchronize")
 
 
+def pimd_graph_info(h):
+    """(state, replays): state 0 not built, 1 replayed, 2 not requested, 3 capture failed."""
+    st, n = C.c_int32(), C.c_int64()
+    _chk(load().pimd_graph_info(h, C.byref(st), C.byref(n)), "pimd_graph_info")
+    return st.value, n.value
+
+
 # ------------------------------------------------------------------ convenience owner
 
 def estimates_dict(e: pimd_estimates) -> Dict[str, float]:
@@ -233,7 +243,7 @@ class Context:
 
     def __init__(self, systems: Sequence[System], precision: str = "mixed", nhc_len: Optional[int] = None,
                  sy_order: int = 3, density_bins: int = 64, density_rmax: float = 6.0, trace_capacity: int = 0,
-                 recursion_workgroups: int = 0, device: str = "cuda:0"):
+                 recursion_workgroups: int = 0, graphs: bool = False, device: str = "cuda:0"):
         import torch  # device memory and streams only
 
         if not systems:
@@ -252,7 +262,8 @@ class Context:
         m = systems[0].nhc_len if nhc_len is None else nhc_len
         self.nhc_len = m
         self.cfg = pimd_config(len(systems), p, dim, PIMD_MIXED if precision == "mixed" else PIMD_FP64, m,
-                               sy_order, density_bins, trace_capacity, recursion_workgroups, 0, density_rmax, reps)
+                               sy_order, density_bins, trace_capacity, recursion_workgroups,
+                               PIMD_FLAG_GRAPH if graphs else 0, density_rmax, reps)
         self.nbytes = pimd_workspace_bytes(self.cfg)
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
@@ -317,6 +328,9 @@ class Context:
 
     def synchronize(self):
         pimd_synchronize(self.h)
+
+    def graph_info(self):
+        return pimd_graph_info(self.h)
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(lib):
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
     assert set(names) == set(lib.EXPORTED)
-    assert lib.pimd_abi_version() == 1
+    assert lib.pimd_abi_version() == 2
 
 
 def _cfg(lib, **over):
@@ -43,10 +43,10 @@ def _cfg(lib, **over):
     for k, v in rep_over.items():
         setattr(reps[1], k, v)
     kw = dict(n_replicas=2, p=12, dim=2, precision=1, nhc_len=4, sy_order=3, density_bins=50,
-              trace_capacity=10, recursion_workgroups=0, reserved=0, density_rmax=5.0)
+              trace_capacity=10, recursion_workgroups=0, flags=0, density_rmax=5.0)
     kw.update(over)
     cfg = lib.pimd_config(kw["n_replicas"], kw["p"], kw["dim"], kw["precision"], kw["nhc_len"], kw["sy_order"],
-                          kw["density_bins"], kw["trace_capacity"], kw["recursion_workgroups"], kw["reserved"],
+                          kw["density_bins"], kw["trace_capacity"], kw["recursion_workgroups"], kw["flags"],
                           kw["density_rmax"], reps)
     return cfg, reps
 
@@ -62,7 +62,7 @@ def test_workspace_size_is_positive_and_monotone(lib):
 @pytest.mark.parametrize("over", [
     {"p": 1}, {"dim": 0}, {"dim": 4}, {"precision": 7}, {"nhc_len": 9}, {"sy_order": 2},
     {"density_bins": 0}, {"density_rmax": 0.0}, {"trace_capacity": -1}, {"n_replicas": 0},
-    {"recursion_workgroups": -1}, {"reserved": 1},
+    {"recursion_workgroups": -1}, {"flags": 2}, {"flags": -1},
     {"rep": {"n": 0}}, {"rep": {"xi": -0.1}}, {"rep": {"xi": 1.5}}, {"rep": {"beta": 0.0}},
     {"rep": {"pair_amp": -1.0}}, {"rep": {"pair_amp": 1.0, "pair_width": 0.0}}, {"rep": {"dt": 0.0}},
     {"rep": {"reserved": 3}}, {"rep": {"mass": -1.0}},
