@@ -105,6 +105,37 @@ def algorithmic_work(kind, systems, P, D):
     return "hbm", dofs, 8, "GB/s", PEAK_HBM_GBS
 
 
+KERNEL_OF_KIND = {("pair", "mixed"): "k_pair_f32", ("pair", "fp64"): "k_pair_f64", ("recursion", "mixed"): "k_recursion",
+                  ("recursion", "fp64"): "k_recursion"}
+
+
+def traffic_bytes(kind, precision, R):
+    """HBM bytes per launch of the kernel from its committed counter record (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a plain device copy of known size), or None
+    when there is no record for this batch size or the kernel's sources changed since it was taken."""
+    import hashlib
+    import re
+    name = KERNEL_OF_KIND.get((kind, precision))
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{name}_large_gauss_counters.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json traffic-record\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("replicas") != R or rec.get("precision") != precision:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(src.encode() + b"\0" + f.read() + b"\0")
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+
+
 def cpu_baseline(sample_steps=12):
     """The CPU oracle as it stands (sequential FP64, one thread) on a bounded sample."""
     import oracle
@@ -163,14 +194,16 @@ def main():
     fp64_sps = args.steps / t64
 
     # mixed batched: choose R by a short sweep unless given
+    curve = {}
     if args.replicas > 0:
         R = args.replicas
     else:
         best, R = 0.0, 1
-        for r in (1, 4, 8, 16, 32, 64):
+        for r in (1, 4, 16, 64, 128, 256):
             n = max(20, args.steps // 10)
             t, _ = run_path("mixed", r, n, 5)
             rate = r * n / t
+            curve[r] = rate
             if rate > best:
                 best, R = rate, r
     tmix, systems = run_path("mixed", R, args.steps, args.warmup)
@@ -210,8 +243,9 @@ def main():
         "fp64_single_bead_updates_per_s": fp64_sps * base.n * base.p,
         "speedup_mixed_batched_vs_fp64": sps / fp64_sps,
         "energy_rel_err_mixed_vs_fp64_same_config": rel,
+        "replica_curve_steps_per_s": curve,
         "roofline": {"kernel": kind, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": None},
+                     "frac": achieved / peak, "traffic": traffic_bytes(kind, "mixed", R)},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

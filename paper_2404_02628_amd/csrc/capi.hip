@@ -96,12 +96,20 @@ void make_plan(const pimd_config* c, Plan& pl) {
   d.R = c->n_replicas; d.P = c->p; d.D = c->dim; d.M = c->nhc_len; d.precision = c->precision;
   d.sy_order = c->sy_order; d.bins = c->density_bins; d.cap = c->trace_capacity; d.rmax = c->density_rmax;
   const int dp = shadow_dp(d.D);
-  // pair split: enough waves to cover the machine (256 CUs x 4 SIMDs x ~2)
-  long long tiles64 = 0;
+  // Pair kernel: with many interacting slices (mixed precision), one workgroup per slice that
+  // evaluates each unordered pair once; otherwise the ordered kernel, split so that there are
+  // enough waves to cover the machine (256 CUs x 4 SIMDs x ~2).
+  long long tiles64 = 0, pair_slices = 0;
+  int pair_maxn = 0;
   for (int r = 0; r < d.R; ++r)
-    if (c->replicas[r].pair_amp > 0) tiles64 += (long long)d.P * ((c->replicas[r].n + 63) / 64);
-  pl.jsplit = tiles64 < 1024 ? 4 : (tiles64 < 2048 ? 2 : 1);
-  const int ipw = 64 * (4 / pl.jsplit);  // particles per pair workgroup
+    if (c->replicas[r].pair_amp > 0) {
+      tiles64 += (long long)d.P * ((c->replicas[r].n + 63) / 64);
+      pair_slices += d.P;
+      pair_maxn = std::max(pair_maxn, c->replicas[r].n);
+    }
+  const bool sym = d.precision == PIMD_MIXED && pair_slices >= 256 && pair_sym_lds_bytes(d.D, pair_maxn) <= 65536;
+  pl.jsplit = sym ? 0 : (tiles64 < 1024 ? 4 : (tiles64 < 2048 ? 2 : 1));
+  const int ipw = sym ? (1 << 30) : 64 * (4 / pl.jsplit);  // particles per pair workgroup
   long long G = 0, NP = 0, XS = 0;
   int maxn = 0;
   pl.reps.resize(d.R);
@@ -142,7 +150,7 @@ void make_plan(const pimd_config* c, Plan& pl) {
     R.pw1 = (long long)pl.pairwork.size();
     for (long long d0 = 0; d0 < R.ndof; d0 += kIntBlock) pl.intwork.push_back(make_int4(r, (int)d0, 0, 0));
   }
-  d.G = G; d.NPtot = NP; d.XStot = XS; d.maxn = maxn;
+  d.G = G; d.NPtot = NP; d.XStot = XS; d.maxn = maxn; d.pair_maxn = pair_maxn;
   d.nspringwg = (long long)pl.springwork.size();
   d.npairwork = (long long)pl.pairwork.size();
   d.nreducewg = d.nspringwg;

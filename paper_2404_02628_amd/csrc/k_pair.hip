@@ -198,9 +198,177 @@ static void launch_pair_js(const Dims& d, const DevPtrs& w, int js, hipStream_t 
   }
 }
 
-// jsplit: waves per 64-particle tile (1, 2 or 4); the work list was built for this value.
+// ------------------------------------------------------------------ symmetric variant
+//
+// One workgroup per slice evaluates every unordered pair once.  The slice is cut into tiles of
+// 64 particles; a wave takes a pair of tiles (I, J) and covers its 64 x 64 pairs as an 8 x 8
+// block per step: lane l pairs particle I[l%8 + 8a] with J[l/8 + 8b] for a, b = 0..7, so the
+// eight i-positions and eight j-positions of a lane stay in registers and each term feeds both
+// sides: F_i += u d and F_j -= u d (Newton's third law per slice), with per-lane accumulators
+// indexed by a and by b.  After the tile pair, a transpose through LDS sums the eight lanes
+// that share a particle (reduce-scatter: lane L ends with the total of particle L of the tile),
+// and the totals are added to the slice's FP64 forces in LDS.  Tile pairs are scheduled as a
+// round-robin tournament (circle method): within a round no two tile pairs share a tile, so
+// the LDS force updates need no atomics and their order is fixed (results are reproducible).
+// The diagonal tiles (I, I) run first with the pairs j <= i masked out.  Padding particles sit
+// at distinct far-away positions, so their terms underflow to exactly zero.
+constexpr int kSymWaves = 4;
+constexpr int kRedStride = 9;   // LDS row stride of the per-wave transpose (conflict-free reads)
+
+template <int D>
+__host__ __device__ inline int sym_lds_bytes(int npad) {
+  constexpr int DP = D == 3 ? 4 : D;
+  return npad * (DP * 4 + D * 8) + kSymWaves * 64 * kRedStride * 4 + 2 * kSymWaves * 8 * 2;
+}
+
+template <int D, bool EST, bool DIAG>
+__device__ inline void sym_tile_pair(const float* __restrict__ pos, double* __restrict__ Fs, float* __restrict__ red,
+                                     int npad, int I, int J, double& Ud, double& Wd) {
+  constexpr int DP = D == 3 ? 4 : D;
+  const int lane = threadIdx.x & 63;
+  const int c0 = lane & 7, k0 = lane >> 3;
+  float xi[8][D], xj[8][D], Fi[8][D], Fj[8][D];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      xi[a][c] = pos[(I * 64 + c0 + 8 * a) * DP + c];
+      xj[a][c] = pos[(J * 64 + k0 + 8 * a) * DP + c];
+      Fi[a][c] = 0.f;
+      Fj[a][c] = 0.f;
+    }
+  }
+  float U = 0.f, W = 0.f;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      float d[D], r2 = 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        d[c] = xi[a][c] - xj[b][c];
+        r2 = __builtin_fmaf(d[c], d[c], r2);
+      }
+      float u = __builtin_amdgcn_exp2f(-r2);
+      if (DIAG) u = (k0 + 8 * b > c0 + 8 * a) ? u : 0.f;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        Fi[a][c] = __builtin_fmaf(u, d[c], Fi[a][c]);
+        Fj[b][c] = __builtin_fmaf(-u, d[c], Fj[b][c]);
+      }
+      if (EST) {
+        U += u;
+        W = __builtin_fmaf(u, r2, W);
+      }
+    }
+  }
+  if (EST) { Ud += (double)U; Wd += (double)W; }
+  // reduce-scatter through LDS: lane L receives the sums for particle L of tile I, then of J
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) red[lane * kRedStride + a] = Fi[a][c];
+    float si = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) si += red[(c0 + 8 * k) * kRedStride + k0];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) red[lane * kRedStride + b] = Fj[b][c];
+    float sj = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sj += red[(q + 8 * c0) * kRedStride + k0];
+    Fs[c * npad + I * 64 + lane] += (double)si;
+    Fs[c * npad + J * 64 + lane] += (double)sj;
+  }
+}
+
+template <int D, bool EST>
+__global__ __launch_bounds__(kSymWaves * 64) void k_pair_sym_f32(const RepDev* __restrict__ reps,
+                                                                 const int4* __restrict__ work,
+                                                                 const float* __restrict__ xs,
+                                                                 double* __restrict__ fpair,
+                                                                 double* __restrict__ pairpart, int P) {
+  constexpr int DP = D == 3 ? 4 : D;
+  extern __shared__ __align__(16) unsigned char sym_lds[];
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const int N = R.n, slice = wk.y, npad = R.npad;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* Fs = reinterpret_cast<double*>(sym_lds);                 // [D][npad]
+  float* pos = reinterpret_cast<float*>(Fs + (long long)D * npad);  // [npad][DP]
+  float* red = pos + (long long)npad * DP + wave * 64 * kRedStride;
+  double* part = reinterpret_cast<double*>(pos + (long long)npad * DP + kSymWaves * 64 * kRedStride);
+  const float* xsl = xs + R.shadow + (long long)slice * npad * DP;
+  for (int l = threadIdx.x; l < npad; l += blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < DP; ++c) pos[l * DP + c] = l < N ? xsl[(long long)l * DP + c] : 1.0e4f * (float)(l + 1);
+#pragma unroll
+    for (int c = 0; c < D; ++c) Fs[c * npad + l] = 0.0;
+  }
+  __syncthreads();
+  const int T = npad / 64;
+  double Ud = 0.0, Wd = 0.0;
+  for (int t = wave; t < T; t += kSymWaves) sym_tile_pair<D, EST, true>(pos, Fs, red, npad, t, t, Ud, Wd);
+  __syncthreads();
+  if (T > 1) {
+    const int Tp = T + (T & 1), m = Tp - 1;
+    for (int r = 0; r < m; ++r) {
+      for (int k = wave; k < Tp / 2; k += kSymWaves) {
+        const int p = k == 0 ? r : (r + k) % m;
+        const int q = k == 0 ? m : (r - k + m) % m;
+        if (p < T && q < T) sym_tile_pair<D, EST, false>(pos, Fs, red, npad, min(p, q), max(p, q), Ud, Wd);
+      }
+      __syncthreads();
+    }
+  }
+  // F = (2A/(P s^2 k)) * sum u (r'_i - r'_j) with r' = k r, k = sqrt(log2 e)/s
+  const double kk = sqrt(1.4426950408889634) / R.width;
+  const double scale = 2.0 * R.amp / ((double)P * R.width * R.width * kk);
+  double* fr = fpair + R.dof;
+  for (int l = threadIdx.x; l < N; l += blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) fr[((long long)c * P + slice) * N + l] = scale * Fs[c * npad + l];
+  }
+  if (EST) {
+    // unordered pairs: U_slice = A sum u, virial part A sum u (1 - r^2/s^2)
+    Ud = wave_sum(Ud);
+    Wd = wave_sum(Wd);
+    if (lane == 0) { part[2 * wave] = Ud; part[2 * wave + 1] = Wd; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double u = 0.0, w = 0.0;
+      for (int q = 0; q < kSymWaves; ++q) { u += part[2 * q]; w += part[2 * q + 1]; }
+      pairpart[2LL * blockIdx.x + 0] = R.amp * u;
+      pairpart[2LL * blockIdx.x + 1] = R.amp * (u - w / 1.4426950408889634);
+    }
+  }
+}
+
+template <int D, bool EST>
+static void launch_pair_sym(const Dims& d, const DevPtrs& w, hipStream_t s) {
+  const int npad = (d.pair_maxn + 63) / 64 * 64;
+  dim3 grid((unsigned)d.npairwork), block(kSymWaves * 64);
+  hipLaunchKernelGGL((k_pair_sym_f32<D, EST>), grid, block, sym_lds_bytes<D>(npad), s, w.reps, w.pairwork, w.xs,
+                     w.fpair, w.pairpart, d.P);
+}
+
+int pair_sym_lds_bytes(int D, int maxn) {
+  const int npad = (maxn + 63) / 64 * 64;
+  return D == 1 ? sym_lds_bytes<1>(npad) : (D == 2 ? sym_lds_bytes<2>(npad) : sym_lds_bytes<3>(npad));
+}
+
+// jsplit: waves per 64-particle tile (1, 2 or 4) of the ordered kernels, or 0 for the symmetric
+// per-slice kernel; the work list was built for this value.
 hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool est, int jsplit, hipStream_t s) {
   if (d.npairwork == 0) return hipSuccess;
+  if (jsplit == 0) {
+    switch (d.D) {
+      case 1: est ? launch_pair_sym<1, true>(d, w, s) : launch_pair_sym<1, false>(d, w, s); break;
+      case 2: est ? launch_pair_sym<2, true>(d, w, s) : launch_pair_sym<2, false>(d, w, s); break;
+      case 3: est ? launch_pair_sym<3, true>(d, w, s) : launch_pair_sym<3, false>(d, w, s); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (d.D) {
     case 1: est ? launch_pair_js<1, true>(d, w, jsplit, s) : launch_pair_js<1, false>(d, w, jsplit, s); break;
     case 2: est ? launch_pair_js<2, true>(d, w, jsplit, s) : launch_pair_js<2, false>(d, w, jsplit, s); break;

@@ -79,7 +79,8 @@ struct Dims {
   long long NPtot;             // sum of npp
   long long XStot;             // floats in the shadow
   long long nspringwg, npairwork, nreducewg, nintwg;
-  int maxn;
+  int maxn;                    // largest N of any replica
+  int pair_maxn;               // largest N of a replica with pair interactions
 };
 
 __host__ __device__ inline int shadow_dp(int D) { return D == 3 ? 4 : D; }
@@ -87,6 +88,7 @@ __host__ __device__ inline int shadow_dp(int D) { return D == 3 ? 4 : D; }
 // Launchers (one per translation unit).
 hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool estimators, int jsplit, hipStream_t s);
+int pair_sym_lds_bytes(int D, int maxn);   // dynamic LDS of the symmetric pair kernel
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, hipStream_t s);
 int recursion_coop_max_blocks_per_cu(int D);
