@@ -55,38 +55,33 @@ def timed_steps(ctx, steps):
     return time.perf_counter() - t0
 
 
-def run_path(precision, R, steps, warmup):
+def run_path(precision, R, steps, warmup, profile=False):
+    """Times `steps` MD steps after `warmup`; with profile, every kernel launch of the timed region
+    is bracketed by HIP events on the stream it runs on, and the per-kind times are returned."""
     ctx, systems = make_ctx(precision, R)
+    times = None
     try:
         ctx.step(warmup, 0)
+        if profile:
+            ctx.profile(True)
         dt = timed_steps(ctx, steps)
+        if profile:
+            times = ctx.kernel_times()
+            ctx.profile(False)
     finally:
         ctx.close()
-    return dt, systems
-
-
-def kernel_profile(precision, R, steps):
-    """Per-kernel average launch time from HIP events bracketing each launch on its stream."""
-    ctx, systems = make_ctx(precision, R)
-    try:
-        ctx.step(5, 0)
-        ctx.profile(True)
-        ctx.step(steps, 0)
-        times = ctx.kernel_times()
-        ctx.profile(False)
-    finally:
-        ctx.close()
-    return times, systems
+    return dt, systems, times
 
 
 def algorithmic_work(kind, systems, P, D):
     """(bound, units per launch, work per unit, unit name, peak) for one kernel kind."""
-    npairs = sum(P * s.n * s.n for s in systems if s.pair_amp > 0)  # ordered pairs incl. self
+    npairs = sum(P * s.n * (s.n - 1) // 2 for s in systems if s.pair_amp > 0)  # unordered pairs
     tri = sum(s.n * (s.n + 1) // 2 for s in systems)
     dofs = sum(D * P * s.n for s in systems)
     if kind == "pair":
-        # per ordered pair: D subtractions, D FMAs (|dr|^2), one exp, D FMAs (force) = 5D + 1 flops
-        return "alu", npairs, 5 * D + 1, "TFLOP/s", PEAK_FP32_TFLOPS
+        # per unordered pair (Eq. 20 counts each once): D subtractions, D FMAs (|dr|^2), one exp,
+        # D FMAs for the force on each of the two particles = 7D + 1 flops (FMA = 2)
+        return "alu", npairs, 7 * D + 1, "TFLOP/s", PEAK_FP32_TFLOPS
     if kind == "recursion":
         # two recursions, each N(N+1)/2 terms; per term (FP64, FMA = 2): distance D + 2D, exponent 4,
         # table exp 17, sum 1, payload sums 2(D+1)  ->  5D + 24 flops
@@ -105,8 +100,8 @@ def algorithmic_work(kind, systems, P, D):
     return "hbm", dofs, 8, "GB/s", PEAK_HBM_GBS
 
 
-KERNEL_OF_KIND = {("pair", "mixed"): "k_pair_f32", ("pair", "fp64"): "k_pair_f64", ("recursion", "mixed"): "k_recursion",
-                  ("recursion", "fp64"): "k_recursion"}
+KERNEL_OF_KIND = {("pair", "mixed"): "k_pair_sym_f32", ("pair", "fp64"): "k_pair_f64",
+                  ("recursion", "mixed"): "k_recursion", ("recursion", "fp64"): "k_recursion"}
 
 
 def traffic_bytes(kind, precision, R):
@@ -190,7 +185,7 @@ def main():
     P, D = base.p, base.dim
 
     # plain FP64 path: one replica
-    t64, _ = run_path("fp64", 1, args.steps, args.warmup)
+    t64, _, _ = run_path("fp64", 1, args.steps, args.warmup)
     fp64_sps = args.steps / t64
 
     # mixed batched: choose R by a short sweep unless given
@@ -201,17 +196,17 @@ def main():
         best, R = 0.0, 1
         for r in (1, 4, 16, 64, 128, 256):
             n = max(20, args.steps // 10)
-            t, _ = run_path("mixed", r, n, 5)
+            t, _, _ = run_path("mixed", r, n, 5)
             rate = r * n / t
             curve[r] = rate
             if rate > best:
                 best, R = rate, r
-    tmix, systems = run_path("mixed", R, args.steps, args.warmup)
+    # the timed region, with per-launch HIP events on each kernel's own stream
+    tmix, systems, times = run_path("mixed", R, args.steps, args.warmup, profile=True)
     sps = R * args.steps / tmix
     beads = sum(s.n * s.p for s in systems)
 
     # roofline of the dominant kernel of the mixed batched step
-    times, systems = kernel_profile("mixed", R, max(20, min(args.steps, 100)))
     dom = max(times.items(), key=lambda kv: kv[1][0])
     kind, (ms_total, launches) = dom[0], dom[1]
     avg_s = ms_total / max(launches, 1) / 1e3

@@ -262,25 +262,27 @@ pimd_status timed(pimd_ctx* c, int kind, hipStream_t st, F&& launch) {
     if (r_ != PIMD_OK) return r_;                                \
   } while (0)
 
-// One force evaluation of every replica at the current positions, enqueued on stream ms.
+// One force evaluation of every replica at the current positions, enqueued on stream ms.  The
+// exchange recursions are launched before the pair kernel (which runs on the second stream), so
+// their few long-lived workgroups are placed first and the pair workgroups fill the rest.
 pimd_status evaluate(pimd_ctx* c, bool est, hipStream_t ms) {
   const Dims& d = c->pl.d;
   const DevPtrs& w = c->w;
   RUN(K_SPRINGS, ms, launch_springs(d, w, ms));
-  const bool fork = c->has_pair && !c->profiling;
-  hipStream_t ps = fork ? c->s2 : ms;
-  if (c->has_pair) {
-    if (fork) {
-      HIPCHK(hipEventRecord(c->ev_fork, ms));
-      HIPCHK(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
-    }
-    RUN(K_PAIR, ps, launch_pair(d, w, est, c->pl.jsplit, ps));
-    if (fork) HIPCHK(hipEventRecord(c->ev_join, c->s2));
-  }
+  const bool fork = c->has_pair;
+  if (fork) HIPCHK(hipEventRecord(c->ev_fork, ms));
   if (c->helpers > 0) RUN(K_RECURSION, ms, launch_recursion_coop(d, w, c->helpers, ms));
   else RUN(K_RECURSION, ms, launch_recursion(d, w, ms));
   RUN(K_REDUCE, ms, launch_probs_reduce(d, w, ms));
-  if (fork) HIPCHK(hipStreamWaitEvent(ms, c->ev_join, 0));
+  if (c->has_pair) {
+    hipStream_t ps = fork ? c->s2 : ms;
+    if (fork) HIPCHK(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+    RUN(K_PAIR, ps, launch_pair(d, w, est, c->pl.jsplit, ps));
+    if (fork) {
+      HIPCHK(hipEventRecord(c->ev_join, c->s2));
+      HIPCHK(hipStreamWaitEvent(ms, c->ev_join, 0));
+    }
+  }
   return PIMD_OK;
 }
 

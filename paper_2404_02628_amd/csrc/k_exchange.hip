@@ -78,9 +78,13 @@ struct RecMap {
   __device__ inline double col_gamma(int j) const { return dir == 0 ? 0.0 : -log((double)(N - j)); }
 };
 
-constexpr int kRecWaves = 8;
-constexpr int kRecThreads = 64 * kRecWaves;
-constexpr int kColsPerWave = kTile / kRecWaves;
+// Waves per recursion workgroup: the cooperative chain kernel uses eight (its block latency is
+// the critical path), the batched kernel four (half the register file and less LDS per CU, so
+// the pair kernel's workgroups can run beside it on the same compute units).
+constexpr int kCoopWaves = 8;
+constexpr int kBatchWaves = 4;
+constexpr int kCoopCols = kTile / kCoopWaves;
+constexpr int kBatchCols = kTile / kBatchWaves;
 
 // How the xi^(i-1-j) factor enters a term: xi = 1 (nothing), xi = 0 (only j = i-1 survives),
 // general xi (exact integer power times log xi).
@@ -205,13 +209,15 @@ __device__ inline double max_term(const RowCtx& rc, const double (&pi)[D], const
 }
 
 // LDS of one recursion workgroup.
-template <int D>
+template <int D, int W>
 struct RecShared {
+  static constexpr int kWaves = W;
+  static constexpr int kCols = kTile / W;   // in-block columns per wave
   double tab[kExpTable];
   double Am[kTile * kTile];             // in-block coefficients, column-major: Am[col * 64 + row]
-  double pm[kRecWaves][kTile], ps[kRecWaves][kTile];
-  double pp[kRecWaves][D + 1][kTile];   // per-wave sums over earlier columns: exp(pm) (ps, pp)
-  double qp[kRecWaves][D + 1][kTile];   // per-wave weighted payloads of the in-block columns
+  double pm[W][kTile], ps[W][kTile];
+  double pp[W][D + 1][kTile];   // per-wave sums over earlier columns: exp(pm) (ps, pp)
+  double qp[W][D + 1][kTile];   // per-wave weighted payloads of the in-block columns
   double Dl[kTile], Wl[kTile];          // row scales D_i and scaled unknowns w_i of the block
   double4 col[2][kTile];                // column records {q_j, gamma_j (+ G_j once solved)}: this block, previous
 };
@@ -225,8 +231,8 @@ struct RowCarry {
   double w, bterm, pb[D + 1];
 };
 
-template <int D>
-__device__ inline void write_avg(const RecShared<D>& sh, const RowCarry<D>& cy, double* __restrict__ av,
+template <int D, class SH>
+__device__ inline void write_avg(const SH& sh, const RowCarry<D>& cy, double* __restrict__ av,
                                  long long npp) {
   if (!cy.valid) return;
   const int lane = threadIdx.x & 63;
@@ -235,20 +241,20 @@ __device__ inline void write_avg(const RecShared<D>& sh, const RowCarry<D>& cy, 
   for (int q = 0; q <= D; ++q) {
     double v = cy.bterm * cy.pb[q];
 #pragma unroll
-    for (int w = 0; w < kRecWaves; ++w) v += sh.qp[w][q][lane];
+    for (int w = 0; w < SH::kWaves; ++w) v += sh.qp[w][q][lane];
     av[(long long)q * npp + cy.i] = v * inv;
   }
 }
 
 // (2a) in-block coefficients alpha_{i,j} (without G_j) from the staged column records; each wave
 // fills its eight columns.
-template <int D>
-__device__ inline void inblock_alpha(RecShared<D>& sh, int cur, int blk, int i, const double (&pi)[D], double rho,
+template <int D, class SH>
+__device__ inline void inblock_alpha(SH& sh, int cur, int blk, int i, const double (&pi)[D], double rho,
                                      bool valid, double bc, double lnxi) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int u = 0; u < kColsPerWave; ++u) {
-    const int sc = wave * kColsPerWave + u;
+  for (int u = 0; u < SH::kCols; ++u) {
+    const int sc = wave * SH::kCols + u;
     const int j = blk * kTile + sc;
     const double4 r4 = sh.col[cur][sc];
     const double qv[3] = {r4.x, r4.y, r4.z};
@@ -317,17 +323,17 @@ __device__ inline double substitute_regs(const double* __restrict__ Am, double a
 // 63 entries per lane-row of work: pass k of wave w takes column s = 4w + k for rows s+1..63 and
 // column 63-s for rows 64-s..63.  Each wave also zeroes the upper triangle of its own eight
 // columns (the substitution reads whole rows).
-template <int D>
-__device__ inline void scaled_coefficients(RecShared<D>& sh) {
+template <int D, class SH>
+__device__ inline void scaled_coefficients(SH& sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int u = 0; u < kColsPerWave; ++u) {
-    const int sc = wave * kColsPerWave + u;
+  for (int u = 0; u < SH::kCols; ++u) {
+    const int sc = wave * SH::kCols + u;
     if (lane <= sc) sh.Am[sc * kTile + lane] = 0.0;
   }
 #pragma unroll
-  for (int k = 0; k < kTile / 2 / kRecWaves; ++k) {
-    const int s = wave * (kTile / 2 / kRecWaves) + k;   // 0..31
+  for (int k = 0; k < kTile / 2 / SH::kWaves; ++k) {
+    const int s = wave * (kTile / 2 / SH::kWaves) + k;   // 0..31
     const bool lower = lane > s;
     const int col = lower ? s : kTile - 1 - s;
     const int row = lower ? lane : kTile - s + lane;     // lanes 0..s-1 -> rows 64-s..63
@@ -340,8 +346,8 @@ __device__ inline void scaled_coefficients(RecShared<D>& sh) {
 
 // G_i, the completed column record of row i (LDS and global), the next block's column records,
 // the publish store and the carried row data; wave 0 only.
-template <int D>
-__device__ inline void finish_rows(RecShared<D>& sh, int blk, int cur, int N, bool valid, double Di, double wi,
+template <int D, class SH>
+__device__ inline void finish_rows(SH& sh, int blk, int cur, int N, bool valid, double Di, double wi,
                                    double bterm, double4* __restrict__ rec, double* __restrict__ G,
                                    const double4& col_next, int* publish, int epoch, RowCarry<D>& cy) {
   const int lane = threadIdx.x & 63;
@@ -373,8 +379,8 @@ __device__ inline void finish_rows(RecShared<D>& sh, int blk, int cur, int N, bo
 // writes G_i, completes the column records (LDS and global), stages the next block's records and
 // publishes the block (release store of `epoch`, when `publish` is set).  All waves then form
 // the in-block weighted payloads (qp).  Wave 1 runs `idle` while wave 0 combines and scales.
-template <int D, class Idle>
-__device__ inline void solve_block(RecShared<D>& sh, int blk, int cur, int N, bool valid, double4* __restrict__ rec,
+template <int D, class SH, class Idle>
+__device__ inline void solve_block(SH& sh, int blk, int cur, int N, bool valid, double4* __restrict__ rec,
                                    double* __restrict__ G, double* __restrict__ av, long long npp,
                                    const double (&pi)[D], const double4& col_next, int* publish, int epoch,
                                    RowCarry<D>& cy, Idle&& idle) {
@@ -386,12 +392,12 @@ __device__ inline void solve_block(RecShared<D>& sh, int blk, int cur, int N, bo
     if (blk > 0) write_avg<D>(sh, cy, av, npp);
     double M = sh.pm[0][lane];
 #pragma unroll
-    for (int w = 1; w < kRecWaves; ++w) M = fmax(M, sh.pm[w][lane]);
+    for (int w = 1; w < SH::kWaves; ++w) M = fmax(M, sh.pm[w][lane]);
     double S = 0.0, PS[D + 1];
 #pragma unroll
     for (int q = 0; q <= D; ++q) PS[q] = 0.0;
 #pragma unroll
-    for (int w = 0; w < kRecWaves; ++w) {
+    for (int w = 0; w < SH::kWaves; ++w) {
       const double f = sh.ps[w][lane] > 0.0 ? fast_exp(sh.pm[w][lane] - M, sh.tab) : 0.0;
       S = fma(sh.ps[w][lane], f, S);
 #pragma unroll
@@ -424,8 +430,8 @@ __device__ inline void solve_block(RecShared<D>& sh, int blk, int cur, int N, bo
 #pragma unroll
     for (int q = 0; q <= D; ++q) Q[q] = 0.0;
 #pragma unroll
-    for (int u = 0; u < kColsPerWave; ++u) {
-      const int sc = wave * kColsPerWave + u;
+    for (int u = 0; u < SH::kCols; ++u) {
+      const int sc = wave * SH::kCols + u;
       const double coef = sh.Am[sc * kTile + lane] * sh.Wl[sc];
       const double4 r4 = sh.col[cur][sc];
       const double qv[3] = {r4.x, r4.y, r4.z};
@@ -486,13 +492,13 @@ struct Prefetch {
 
 // One workgroup per replica and direction (batched replicas fill the machine).
 template <int D>
-__global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restrict__ reps,
+__global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __restrict__ reps,
                                                            const double* __restrict__ ends,
                                                            const double* __restrict__ link,
                                                            double* __restrict__ gf, double* __restrict__ gb,
                                                            double4* __restrict__ colrec,
                                                            double* __restrict__ avg) {
-  __shared__ RecShared<D> sh;
+  __shared__ RecShared<D, kBatchWaves> sh;
   const int rep = blockIdx.x >> 1, dir = blockIdx.x & 1;
   const RepDev& R = reps[rep];
   const int N = R.n;
@@ -531,9 +537,9 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restr
       double mx = -INFINITY;
       if (valid) {
         const double4* cp = sh.col[cur ^ 1];
-        const int j0 = wave * kColsPerWave;
+        const int j0 = wave * kBatchCols;
 #pragma unroll
-        for (int u = 0; u < kColsPerWave; ++u) {
+        for (int u = 0; u < kBatchCols; ++u) {
           double d2;
           const double4 r4 = cp[j0 + u];
           const int j = jend - kTile + j0 + u;
@@ -548,7 +554,7 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restr
       __syncthreads();
       mx = sh.pm[0][lane];
 #pragma unroll
-      for (int w = 1; w < kRecWaves; ++w) mx = fmax(mx, sh.pm[w][lane]);
+      for (int w = 1; w < kBatchWaves; ++w) mx = fmax(mx, sh.pm[w][lane]);
       Rref = (mx > -INFINITY) ? mx : 0.0;
       __syncthreads();
     }
@@ -558,7 +564,7 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion(const RepDev* __restr
 #pragma unroll
     for (int q = 0; q <= D; ++q) P[q] = 0.0;
     if (valid && jend > 0) {
-      const int per = (jend + kRecWaves - 1) / kRecWaves;
+      const int per = (jend + kBatchWaves - 1) / kBatchWaves;
       const int ja = min(jend, wave * per), jb = min(jend, ja + per);
       if (xm == kXiOne) bulk_rows<D, kXiOne>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
       else if (xm == kXiZero) bulk_rows<D, kXiZero>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
@@ -607,14 +613,14 @@ __device__ inline bool wait_epoch(const int* flag, int epoch, int* err) {
 
 // Folds columns [j0, j0 + n) into the running log-sum-exp (m, s, P): one rescale per slice.
 // `recs` points at the record of column j0 (global or LDS).
-template <int D, int XM>
+template <int D, int XM, int NC>
 __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const double4* recs, int j0, int n,
                                   const double* tab, double& m, double& s, double (&P)[D + 1]) {
-  double t[kColsPerWave], d2[kColsPerWave];
-  double4 r[kColsPerWave];
+  double t[NC], d2[NC];
+  double4 r[NC];
   double mt = -INFINITY;
 #pragma unroll
-  for (int u = 0; u < kColsPerWave; ++u) {
+  for (int u = 0; u < NC; ++u) {
     r[u] = recs[min(u, n - 1)];
     t[u] = term_of<D, XM>(rc, pi, r[u], j0 + u, d2[u]);
     if (u >= n) t[u] = -INFINITY;
@@ -627,7 +633,7 @@ __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const
   for (int q = 0; q <= D; ++q) P[q] *= f;
   m = M;
 #pragma unroll
-  for (int u = 0; u < kColsPerWave; ++u) {
+  for (int u = 0; u < NC; ++u) {
     const double e = fast_exp(t[u] - M, tab);
     s += e;
     const double qv[3] = {r[u].x, r[u].y, r[u].z};
@@ -637,16 +643,16 @@ __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const
   }
 }
 
-template <int D>
+template <int D, int NC>
 __device__ inline void fold_any(int xm, const RowCtx& rc, const double (&pi)[D], const double4* recs, int j0, int n,
                                 const double* tab, double& m, double& s, double (&P)[D + 1]) {
-  if (xm == kXiOne) slice_fold<D, kXiOne>(rc, pi, recs, j0, n, tab, m, s, P);
-  else if (xm == kXiZero) slice_fold<D, kXiZero>(rc, pi, recs, j0, n, tab, m, s, P);
-  else slice_fold<D, kXiGen>(rc, pi, recs, j0, n, tab, m, s, P);
+  if (xm == kXiOne) slice_fold<D, kXiOne, NC>(rc, pi, recs, j0, n, tab, m, s, P);
+  else if (xm == kXiZero) slice_fold<D, kXiZero, NC>(rc, pi, recs, j0, n, tab, m, s, P);
+  else slice_fold<D, kXiGen, NC>(rc, pi, recs, j0, n, tab, m, s, P);
 }
 
 template <int D>
-__global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __restrict__ reps,
+__global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev* __restrict__ reps,
                                                                 const double* __restrict__ ends,
                                                                 const double* __restrict__ link,
                                                                 double* __restrict__ gf, double* __restrict__ gb,
@@ -654,7 +660,7 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
                                                                 double* __restrict__ avg, int* __restrict__ flags,
                                                                 double* __restrict__ partial, int* __restrict__ err,
                                                                 int nchains, int H) {
-  __shared__ RecShared<D> sh;
+  __shared__ RecShared<D, kCoopWaves> sh;
   const int epoch = err[1];   // stamp of this evaluation (advanced by the spring kernel)
   const bool is_chain = (int)blockIdx.x < nchains;
   const int chain = is_chain ? (int)blockIdx.x : ((int)blockIdx.x - nchains) % nchains;
@@ -704,8 +710,8 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
       for (int q = 0; q <= D; ++q) P[q] = 0.0;
       // the panel just finished (columns of block blk-1, in LDS), one 8-column slice per wave
       if (blk >= 1 && valid)
-        fold_any<D>(xm, rc, pi, sh.col[cur ^ 1] + wave * kColsPerWave, (blk - 1) * kTile + wave * kColsPerWave,
-                    kColsPerWave, sh.tab, m, s, P);
+        fold_any<D, kCoopCols>(xm, rc, pi, sh.col[cur ^ 1] + wave * kCoopCols, (blk - 1) * kTile + wave * kCoopCols,
+                    kCoopCols, sh.tab, m, s, P);
       if (have_part && hs > 0.0) {
         const double M = fmax(m, hm);
         const double f0 = fast_exp(m - M, sh.tab), f1 = fast_exp(hm - M, sh.tab);
@@ -775,8 +781,8 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
         if (ready < 0) return;   // a wait failed: the error word is raised, stop this helper
       }
       if (valid) {
-        const int j0 = c * kTile + wave * kColsPerWave;
-        fold_any<D>(xm, rc, pi, rec + j0, j0, kColsPerWave, sh.tab, m, s, P);
+        const int j0 = c * kTile + wave * kCoopCols;
+        fold_any<D, kCoopCols>(xm, rc, pi, rec + j0, j0, kCoopCols, sh.tab, m, s, P);
       }
     }
     sh.pm[wave][lane] = m;
@@ -787,12 +793,12 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
     if (wave == 0 && valid) {
       double M = sh.pm[0][lane];
 #pragma unroll
-      for (int w = 1; w < kRecWaves; ++w) M = fmax(M, sh.pm[w][lane]);
+      for (int w = 1; w < kCoopWaves; ++w) M = fmax(M, sh.pm[w][lane]);
       double S = 0.0, PS[D + 1];
 #pragma unroll
       for (int q = 0; q <= D; ++q) PS[q] = 0.0;
 #pragma unroll
-      for (int w = 0; w < kRecWaves; ++w) {
+      for (int w = 0; w < kCoopWaves; ++w) {
         const double f = sh.ps[w][lane] > 0.0 ? fast_exp(sh.pm[w][lane] - M, sh.tab) : 0.0;
         S = fma(sh.ps[w][lane], f, S);
 #pragma unroll
@@ -809,7 +815,7 @@ __global__ __launch_bounds__(kRecThreads) void k_recursion_coop(const RepDev* __
 }
 
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s) {
-  dim3 grid((unsigned)(2 * d.R)), block(kRecThreads);
+  dim3 grid((unsigned)(2 * d.R)), block(64 * kBatchWaves);
 #define L(DD) hipLaunchKernelGGL(k_recursion<DD>, grid, block, 0, s, w.reps, w.ends, w.link, w.gf, w.gb, w.colrec, w.avg)
   switch (d.D) {
     case 1: L(1); break;
@@ -824,7 +830,7 @@ hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s) {
 template <int D>
 static hipError_t launch_coop_d(const Dims& d, const DevPtrs& w, int H, hipStream_t s) {
   int nchains = 2 * d.R;
-  dim3 grid((unsigned)(nchains * (1 + H))), block(kRecThreads);
+  dim3 grid((unsigned)(nchains * (1 + H))), block(64 * kCoopWaves);
   const RepDev* reps = w.reps;
   const double* ends = w.ends;
   const double* link = w.link;
@@ -852,9 +858,9 @@ hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, h
 int recursion_coop_max_blocks_per_cu(int D) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
-  if (D == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<1>, kRecThreads, 0);
-  if (D == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<2>, kRecThreads, 0);
-  if (D == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<3>, kRecThreads, 0);
+  if (D == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<1>, 64 * kCoopWaves, 0);
+  if (D == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<2>, 64 * kCoopWaves, 0);
+  if (D == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<3>, 64 * kCoopWaves, 0);
   return e == hipSuccess ? n : 0;
 }
 

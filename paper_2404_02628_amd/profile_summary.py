@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # Sources whose change invalidates a kernel's counter record.
 KERNEL_SOURCES = {
+    "k_pair_sym_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h"],
     "k_pair_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h"],
     "k_pair_f64": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h"],
     "k_recursion": ["paper_2404_02628_amd/csrc/k_exchange.hip", "paper_2404_02628_amd/csrc/fast_exp.h",
@@ -120,8 +121,8 @@ def counters(fetch_dir, write_dir, copy_mib, kernel, replicas, precision):
         mb = (statistics.fmean(fv) * fs + statistics.fmean(wv) * ws) * 1024 / 1e6
         lines.append(f"| `{k}` | {g} | {len(fv)} | {statistics.fmean(fv):.1f} | {statistics.fmean(wv):.1f} | {mb:.2f} |")
     rec = None
-    kf = [v for kk, vals in fk.items() if kk.startswith(kernel) for v, _ in vals]
-    kw = [v for kk, vals in wk.items() if kk.startswith(kernel) for v, _ in vals]
+    kf = [v for kk, vals in fk.items() if kk.split("<")[0] == kernel for v, _ in vals]
+    kw = [v for kk, vals in wk.items() if kk.split("<")[0] == kernel for v, _ in vals]
     if kf and kw:
         srcs = KERNEL_SOURCES.get(kernel, [])
         rec = {"kernel": kernel, "replicas": replicas, "precision": precision,
