@@ -4,9 +4,11 @@
 
 runs, in order: a plain device-to-device copy of --copy-mib MiB (torch, known traffic: that
 many bytes read and written), used to scale the FETCH_SIZE / WRITE_SIZE counters to bytes;
-then --steps MD steps of the N=1600, P=32 Gaussian workload on the chosen path (mixed or
-fp64, R replicas, recursion schedule --workgroups), after --warmup untimed steps.  It prints
-one line per phase so a profiled run can be matched to its dispatches.
+then --steps MD steps of a workload on the chosen path (mixed or fp64, recursion schedule
+--workgroups), after --warmup untimed steps: --replicas copies (seeds base+r) of a named
+workload (default the N=1600, P=32 Gaussian system), or with --workload batched the 64
+uneven replicas (N ~ U{64..512}, xi = 0.2 (1 + r mod 5)).  It prints one line per phase so a
+profiled run can be matched to its dispatches, and the workspace size.
 """
 from __future__ import annotations
 
@@ -24,12 +26,13 @@ def main(argv=None) -> int:
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--workload", default="large_gauss")
     ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--graphs", action="store_true", help="replay steady steps from a HIP graph")
     args = ap.parse_args(argv)
 
     import torch
 
     from .pimd import Context
-    from .workloads import WORKLOADS, initial_state
+    from .workloads import WORKLOADS, batched_systems, initial_state
 
     n = args.copy_mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -40,20 +43,26 @@ def main(argv=None) -> int:
     print(f"copy {args.copy_mib} MiB done", flush=True)
     del src, dst
 
-    base = WORKLOADS[args.workload]
-    systems = [base.with_(seed=base.seed + r) for r in range(args.replicas)]
-    ctx = Context(systems, precision=args.path, recursion_workgroups=args.workgroups)
-    for r, s in enumerate(systems):
-        x, p = initial_state(s)
+    if args.workload == "batched":
+        systems = batched_systems(64, 505)
+    else:
+        base = WORKLOADS[args.workload]
+        systems = [base.with_(seed=base.seed + r) for r in range(args.replicas)]
+    ctx = Context(systems, precision=args.path, recursion_workgroups=args.workgroups, graphs=args.graphs)
+    for r, sy in enumerate(systems):
+        x, p = initial_state(sy)
         ctx.set_state(r, x, p)
+    print(f"workspace {ctx.nbytes / 2**20:.1f} MiB for {len(systems)} replicas", flush=True)
     ctx.step(args.warmup, 0)
     ctx.synchronize()
     t0 = time.perf_counter()
     ctx.step(args.steps, 0)
     ctx.synchronize()
     dt = time.perf_counter() - t0
-    print(f"{args.path} R={args.replicas} {args.steps} steps {dt * 1e3:.2f} ms "
-          f"({args.replicas * args.steps / dt:.1f} replica-steps/s)", flush=True)
+    beads = sum(sy.n * sy.p for sy in systems)
+    print(f"{args.workload} {args.path}{' graphs' if args.graphs else ''} R={len(systems)} {args.steps} steps {dt * 1e3:.2f} ms "
+          f"({len(systems) * args.steps / dt:.1f} replica-steps/s, {beads * args.steps / dt:.3e} bead-updates/s)",
+          flush=True)
     ctx.close()
     return 0
 
