@@ -32,12 +32,17 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (published)
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E (published)
 
 
-def make_ctx(precision, R, nhc_len=4):
-    from paper_2404_02628_amd.pimd import Context
+def bench_systems(R):
     base = WORKLOADS["large_gauss"]
-    systems = [base.with_(seed=base.seed + r) for r in range(R)]
+    return [base.with_(seed=base.seed + r) for r in range(R)]
+
+
+def make_ctx(precision, R, nhc_len=4, knobs=None):
+    from paper_2404_02628_amd.pimd import Context
+    systems = bench_systems(R)
+    kw = knobs.as_kwargs() if knobs is not None else {}
     ctx = Context(systems, precision=precision, nhc_len=nhc_len, density_bins=64, density_rmax=8.0,
-                  trace_capacity=0)
+                  trace_capacity=0, **kw)
     for r, s in enumerate(systems):
         x, p = initial_state(s)
         ctx.set_state(r, x, p)
@@ -55,10 +60,10 @@ def timed_steps(ctx, steps):
     return time.perf_counter() - t0
 
 
-def run_path(precision, R, steps, warmup, profile=False):
+def run_path(precision, R, steps, warmup, profile=False, knobs=None):
     """Times `steps` MD steps after `warmup`; with profile, every kernel launch of the timed region
     is bracketed by HIP events on the stream it runs on, and the per-kind times are returned."""
-    ctx, systems = make_ctx(precision, R)
+    ctx, systems = make_ctx(precision, R, knobs=knobs)
     times = None
     try:
         ctx.step(warmup, 0)
@@ -184,8 +189,11 @@ def main():
     base = WORKLOADS["large_gauss"]
     P, D = base.p, base.dim
 
-    # plain FP64 path: one replica
-    t64, _, _ = run_path("fp64", 1, args.steps, args.warmup)
+    from paper_2404_02628_amd import autotune
+
+    # plain FP64 path: one replica, with its own best launch choices
+    tune64 = autotune.tune(bench_systems(1), "fp64", steps=20, warmup=5)
+    t64, _, _ = run_path("fp64", 1, args.steps, args.warmup, knobs=tune64.best)
     fp64_sps = args.steps / t64
 
     # mixed batched: choose R by a short sweep unless given
@@ -201,8 +209,15 @@ def main():
             curve[r] = rate
             if rate > best:
                 best, R = rate, r
-    # the timed region, with per-launch HIP events on each kernel's own stream
-    tmix, systems, times = run_path("mixed", R, args.steps, args.warmup, profile=True)
+    # launch choices for that batch, then the timed region with per-launch HIP events on each
+    # kernel's own stream (a graph-replayed best choice is timed without events, and the events
+    # come from a second run of the same choice with direct launches)
+    tunemix = autotune.tune(bench_systems(R), "mixed", steps=10, warmup=3)
+    best = tunemix.best
+    tmix, systems, times = run_path("mixed", R, args.steps, args.warmup, profile=not best.graphs, knobs=best)
+    if best.graphs:
+        _, _, times = run_path("mixed", R, args.steps, args.warmup, profile=True,
+                               knobs=autotune.Knobs(best.recursion_workgroups, best.pair_kernel, False))
     sps = R * args.steps / tmix
     beads = sum(s.n * s.p for s in systems)
 
@@ -239,6 +254,10 @@ def main():
         "speedup_mixed_batched_vs_fp64": sps / fp64_sps,
         "energy_rel_err_mixed_vs_fp64_same_config": rel,
         "replica_curve_steps_per_s": curve,
+        "autotune": {"mixed": {"best": best.as_kwargs(),
+                               "s_per_step": {str(k.as_kwargs()): v for k, v in tunemix.seconds_per_step.items()}},
+                     "fp64": {"best": tune64.best.as_kwargs(),
+                              "s_per_step": {str(k.as_kwargs()): v for k, v in tune64.seconds_per_step.items()}}},
         "roofline": {"kernel": kind, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic_bytes(kind, "mixed", R)},
         "kernels": kernels,

@@ -66,6 +66,9 @@ typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
 
 /* pimd_config.flags */
 #define PIMD_FLAG_GRAPH 1      /* replay steady MD steps from a captured HIP graph (default: direct launches) */
+#define PIMD_FLAG_PAIR_ORDERED 2  /* use the ordered pair kernel even where the symmetric
+                                     per-slice kernel would be chosen (mixed precision with at
+                                     least 256 interacting slices); for tuning and testing */
 
 /* One independent system (replica).  Units are free; the paper uses
  * hbar = m = omega = k_B = 1 (Sec. IV.A). */

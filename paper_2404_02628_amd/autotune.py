@@ -1,0 +1,94 @@
+"""Autotuning of the launch choices that the library leaves to the caller.
+
+For a fixed set of replicas the knobs are the recursion schedule (`recursion_workgroups`: 0 lets
+the library choose, 1 forces one workgroup per replica and direction, k > 1 a cooperative chain
+with k-1 helpers), the pair kernel (the symmetric per-slice kernel where the library would pick
+it, or the ordered one) and replay of steady steps from a HIP graph.  `tune` times every
+candidate for a few MD steps on the device and returns the fastest; `tune_replicas` picks the
+batch size (replica count) with the highest aggregate replica-steps/s.  Both measure, so they
+need a GPU; `candidates` and `pick` are plain functions that tests exercise without one.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, Iterable, List, Optional, Sequence
+
+from .workloads import System, initial_state
+
+
+@dataclass(frozen=True)
+class Knobs:
+    recursion_workgroups: int = 0
+    pair_kernel: str = "auto"
+    graphs: bool = False
+
+    def as_kwargs(self) -> Dict:
+        return {"recursion_workgroups": self.recursion_workgroups, "pair_kernel": self.pair_kernel,
+                "graphs": self.graphs}
+
+
+@dataclass
+class TuneResult:
+    best: Knobs
+    seconds_per_step: Dict[Knobs, float] = field(default_factory=dict)
+
+
+def candidates(systems: Sequence[System], precision: str) -> List[Knobs]:
+    """The candidate set for these replicas: schedules that differ in practice only."""
+    has_pair = any(s.pair_amp > 0 for s in systems)
+    nblk = max((s.n + 64) // 64 for s in systems)
+    scheds = [0, 1]
+    if len(systems) <= 8 and nblk > 2:
+        # a few cooperative helper counts between "one helper" and "as many as fit"
+        scheds += sorted({h + 1 for h in (1, 4, 16) if h < nblk - 1})
+    pairs = ["auto", "ordered"] if (has_pair and precision == "mixed" and
+                                    sum(s.p for s in systems if s.pair_amp > 0) >= 256) else ["auto"]
+    out = []
+    for r in scheds:
+        for pk in pairs:
+            for g in (False, True):
+                out.append(Knobs(r, pk, g))
+    return out
+
+
+def pick(timings: Dict[Knobs, float]) -> Knobs:
+    """Fastest candidate; ties go to the simpler one (library defaults first)."""
+    def simplicity(k: Knobs):
+        return (k.graphs, k.pair_kernel != "auto", k.recursion_workgroups != 0, k.recursion_workgroups)
+    return min(timings, key=lambda k: (timings[k], simplicity(k)))
+
+
+def _time_steps(systems, precision, knobs: Knobs, steps: int, warmup: int, **ctx_kw) -> float:
+    from .pimd import Context
+    ctx = Context(systems, precision=precision, **knobs.as_kwargs(), **ctx_kw)
+    try:
+        for r, s in enumerate(systems):
+            x, p = initial_state(s)
+            ctx.set_state(r, x, p)
+        ctx.step(warmup, 0)
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(steps, 0)
+        ctx.synchronize()
+        return (time.perf_counter() - t0) / steps
+    finally:
+        ctx.close()
+
+
+def tune(systems: Sequence[System], precision: str = "mixed", steps: int = 20, warmup: int = 5,
+         cands: Optional[Iterable[Knobs]] = None, **ctx_kw) -> TuneResult:
+    timings = {}
+    for k in (list(cands) if cands is not None else candidates(systems, precision)):
+        timings[k] = _time_steps(systems, precision, k, steps, warmup, **ctx_kw)
+    return TuneResult(pick(timings), timings)
+
+
+def tune_replicas(make_systems: Callable[[int], List[System]], counts: Sequence[int], precision: str = "mixed",
+                  steps: int = 20, warmup: int = 5, **ctx_kw) -> Dict[int, float]:
+    """Aggregate replica-steps/s for each replica count (library-default knobs)."""
+    out = {}
+    for R in counts:
+        systems = make_systems(R)
+        out[R] = R / _time_steps(systems, precision, Knobs(), steps, warmup, **ctx_kw)
+    return out

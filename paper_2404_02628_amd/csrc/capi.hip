@@ -71,7 +71,7 @@ pimd_status validate(const pimd_config* c) {
   if (c->trace_capacity < 0) return fail(PIMD_ERR_INVALID, "trace_capacity must be >= 0");
   if (c->recursion_workgroups < 0 || c->recursion_workgroups > 4096)
     return fail(PIMD_ERR_INVALID, "recursion_workgroups must be in 0..4096");
-  if ((c->flags & ~PIMD_FLAG_GRAPH) != 0) return fail(PIMD_ERR_INVALID, "unknown bits in flags");
+  if ((c->flags & ~(PIMD_FLAG_GRAPH | PIMD_FLAG_PAIR_ORDERED)) != 0) return fail(PIMD_ERR_INVALID, "unknown bits in flags");
   for (int r = 0; r < c->n_replicas; ++r) {
     const pimd_replica& q = c->replicas[r];
     std::string where = "replica " + std::to_string(r) + ": ";
@@ -107,7 +107,8 @@ void make_plan(const pimd_config* c, Plan& pl) {
       pair_slices += d.P;
       pair_maxn = std::max(pair_maxn, c->replicas[r].n);
     }
-  const bool sym = d.precision == PIMD_MIXED && pair_slices >= 256 && pair_sym_lds_bytes(d.D, pair_maxn) <= 65536;
+  const bool sym = d.precision == PIMD_MIXED && pair_slices >= 256 && pair_sym_lds_bytes(d.D, pair_maxn) <= 65536 &&
+                   (c->flags & PIMD_FLAG_PAIR_ORDERED) == 0;
   pl.jsplit = sym ? 0 : (tiles64 < 1024 ? 4 : (tiles64 < 2048 ? 2 : 1));
   const int ipw = sym ? (1 << 30) : 64 * (4 / pl.jsplit);  // particles per pair workgroup
   long long G = 0, NP = 0, XS = 0;

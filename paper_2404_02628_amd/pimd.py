@@ -24,6 +24,7 @@ PIMD_OK, PIMD_ERR_INVALID, PIMD_ERR_DEVICE, PIMD_ERR_NONFINITE, PIMD_ERR_WORKSPA
 PIMD_FP64, PIMD_MIXED = 0, 1
 PIMD_HOST, PIMD_DEVICE = 0, 1
 PIMD_FLAG_GRAPH = 1
+PIMD_FLAG_PAIR_ORDERED = 2
 
 EXPORTED = [
     "pimd_abi_version", "pimd_last_error", "pimd_workspace_bytes", "pimd_create", "pimd_destroy",
@@ -243,11 +244,14 @@ class Context:
 
     def __init__(self, systems: Sequence[System], precision: str = "mixed", nhc_len: Optional[int] = None,
                  sy_order: int = 3, density_bins: int = 64, density_rmax: float = 6.0, trace_capacity: int = 0,
-                 recursion_workgroups: int = 0, graphs: bool = False, device: str = "cuda:0"):
+                 recursion_workgroups: int = 0, graphs: bool = False, pair_kernel: str = "auto",
+                 device: str = "cuda:0"):
         import torch  # device memory and streams only
 
         if not systems:
             raise ValueError("need at least one system")
+        if pair_kernel not in ("auto", "ordered"):
+            raise ValueError("pair_kernel must be 'auto' or 'ordered'")
         p, dim = systems[0].p, systems[0].dim
         if any(s.p != p or s.dim != dim for s in systems):
             raise ValueError("all replicas of one context share P and dim")
@@ -263,7 +267,8 @@ class Context:
         self.nhc_len = m
         self.cfg = pimd_config(len(systems), p, dim, PIMD_MIXED if precision == "mixed" else PIMD_FP64, m,
                                sy_order, density_bins, trace_capacity, recursion_workgroups,
-                               PIMD_FLAG_GRAPH if graphs else 0, density_rmax, reps)
+                               (PIMD_FLAG_GRAPH if graphs else 0) |
+                               (PIMD_FLAG_PAIR_ORDERED if pair_kernel == "ordered" else 0), density_rmax, reps)
         self.nbytes = pimd_workspace_bytes(self.cfg)
         self.device = torch.device(device)
         with torch.cuda.device(self.device):

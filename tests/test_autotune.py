@@ -1,0 +1,24 @@
+"""Candidate generation and selection of the autotuner (host logic; the timing itself needs a GPU)."""
+from paper_2404_02628_amd.autotune import Knobs, candidates, pick
+from paper_2404_02628_amd.workloads import WORKLOADS, batched_systems
+
+
+def test_candidates_cover_the_schedules_that_apply():
+    big = WORKLOADS["large_gauss"]
+    one = candidates([big], "fp64")
+    assert Knobs(0, "auto", False) in one and Knobs(1, "auto", True) in one
+    assert any(k.recursion_workgroups > 1 for k in one)          # cooperative helper counts
+    assert all(k.pair_kernel == "auto" for k in one)             # FP64: ordered kernel only
+    many = candidates([big.with_(seed=k) for k in range(16)], "mixed")
+    assert {k.pair_kernel for k in many} == {"auto", "ordered"}  # 512 slices: both pair kernels
+    assert all(k.recursion_workgroups in (0, 1) for k in many)   # batched: no helpers
+    tiny = candidates([WORKLOADS["small_ideal"]], "fp64")
+    assert all(k.recursion_workgroups in (0, 1) for k in tiny)   # one row block: nothing to help
+    assert len(set(candidates(batched_systems(64, 505), "mixed"))) == len(candidates(batched_systems(64, 505), "mixed"))
+
+
+def test_pick_takes_the_fastest_and_breaks_ties_toward_defaults():
+    t = {Knobs(0, "auto", False): 2.0, Knobs(1, "ordered", True): 1.0, Knobs(5, "auto", False): 3.0}
+    assert pick(t) == Knobs(1, "ordered", True)
+    t = {Knobs(1, "auto", True): 1.0, Knobs(0, "auto", False): 1.0, Knobs(1, "auto", False): 1.0}
+    assert pick(t) == Knobs(0, "auto", False)
