@@ -140,6 +140,12 @@ void make_plan(const pimd_config* c, Plan& pl) {
     R.lnxi = q.xi > 0 ? std::log(q.xi) : -INFINITY;
     R.mw2 = q.mass * q.omega * q.omega;
     R.inv_s2 = q.pair_amp > 0 ? 1.0 / (q.pair_width * q.pair_width) : 0.0;
+    R.inv_mp = 1.0 / R.mp;
+    R.inv_q = 1.0 / R.q;
+    R.kT = 1.0 / q.beta;
+    R.dt_mp = q.dt / R.mp;
+    R.trap_p = R.mw2 / (double)d.P;
+    R.pair_k = (float)(q.pair_amp > 0 ? std::sqrt(1.4426950408889634) / q.pair_width : 1.0);
     R.spw0 = (long long)pl.springwork.size();
     for (int l0 = 0; l0 < q.n; l0 += kSpringBlock) pl.springwork.push_back(make_int4(r, l0, 0, 0));
     R.spw1 = (long long)pl.springwork.size();

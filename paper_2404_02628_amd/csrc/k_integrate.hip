@@ -15,6 +15,23 @@ namespace pimd {
 
 struct SyW { double w[5]; int n; };
 
+// exp(x) for the thermostat scale factors, whose arguments (h v / 4 and h v with h a fraction
+// of dt) are small: when every lane of the wavefront has |x| <= 1/32 the Taylor polynomial of
+// degree 8 (remainder below 2e-19 relative) replaces the table-driven exponential.
+__device__ inline double chain_exp(double x, const double* tab) {
+  if (__all(fabs(x) <= 0.03125)) {
+    double q = fma(x, 1.0 / 40320.0, 1.0 / 5040.0);
+    q = fma(q, x, 1.0 / 720.0);
+    q = fma(q, x, 1.0 / 120.0);
+    q = fma(q, x, 1.0 / 24.0);
+    q = fma(q, x, 1.0 / 6.0);
+    q = fma(q, x, 0.5);
+    q = fma(q, x, 1.0);
+    return fma(q, x, 1.0);
+  }
+  return fast_exp(x, tab);
+}
+
 // The chain forces are G_1 = (p^2/m' - kT)/Q and G_k = (Q v_{k-1}^2 - kT)/Q = v_{k-1}^2 - kT/Q,
 // evaluated with precomputed reciprocals.  The scale factor exp(-h v_{k+1}/4) of element k is
 // the same number in the inward and the outward sweep (v_{k+1} is not touched in between), so
@@ -30,11 +47,11 @@ __device__ inline void nhc_propagate(double& p, double inv_mp, double* eta, doub
       v[M - 1] += 0.5 * h * Gm;
     }
     for (int k = M - 2; k >= 0; --k) {
-      sc[k] = fast_exp(-0.25 * h * v[k + 1], tab);
+      sc[k] = chain_exp(-0.25 * h * v[k + 1], tab);
       double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
       v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];
     }
-    p *= fast_exp(-h * v[0], tab);
+    p *= chain_exp(-h * v[0], tab);
     for (int k = 0; k < M; ++k) eta[k] += h * v[k];
     for (int k = 0; k <= M - 2; ++k) {
       double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
@@ -54,7 +71,7 @@ __device__ inline void nhc_half(double& p, const RepDev& R, double* eta, double*
   double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
 #pragma unroll
   for (int k = 0; k < M; ++k) { e[k] = eta[k * G + gi]; v[k] = veta[k * G + gi]; }
-  nhc_propagate(p, 1.0 / R.mp, e, v, M, 1.0 / R.q, 1.0 / R.beta, 0.5 * R.dt, sy, tab);
+  nhc_propagate(p, R.inv_mp, e, v, M, R.inv_q, R.kT, 0.5 * R.dt, sy, tab);
 #pragma unroll
   for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
 }
@@ -86,13 +103,15 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
     double pv = p[gi];
     nhc_half<M>(pv, R, eta, veta, gi, G, sy, tab);
     pv += hdt * f[gi];
-    x[gi] += R.dt * pv / R.mp;
+    x[gi] += R.dt_mp * pv;
     p[gi] = pv;
     return;
   }
   double fv = f[gi];
   if (R.amp > 0.0) fv += fpair[gi];
-  f[gi] = fv;
+  // the total force is kept for readers of the last evaluation; in the fused pass the next
+  // evaluation overwrites it unread
+  if (MODE != 3) f[gi] = fv;
   if (MODE == 2) return;
   double pv = p[gi] + hdt * fv;
   if (MODE == 1) {
@@ -105,14 +124,13 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
     double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
 #pragma unroll
     for (int k = 0; k < M; ++k) { e[k] = eta[k * G + gi]; v[k] = veta[k * G + gi]; }
-    const double inv_mp = 1.0 / R.mp, inv_q = 1.0 / R.q, kT = 1.0 / R.beta;
-    nhc_propagate(pv, inv_mp, e, v, M, inv_q, kT, hdt, sy, tab);
-    nhc_propagate(pv, inv_mp, e, v, M, inv_q, kT, hdt, sy, tab);
+    nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
 #pragma unroll
     for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
   }
   pv += hdt * fv;
-  x[gi] += R.dt * pv / R.mp;
+  x[gi] += R.dt_mp * pv;
   p[gi] = pv;
 }
 

@@ -40,11 +40,11 @@ __global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restri
   if (l < N) {
     const double* xr = x + R.dof;
     double* fr = f + R.dof;
-    const double kap = R.kappa, trap = R.mw2 / (double)P;
+    const double kap = R.kappa, trap = R.trap_p;
     double e_int = 0.0, lk = 0.0, ut = 0.0;
     double* a_out = ends + 2LL * D * R.part;
     double* b_out = a_out + (long long)D * R.npp;
-    const float kscale = (float)(R.amp > 0.0 ? sqrt(1.4426950408889634) / R.width : 1.0);
+    const float kscale = R.pair_k;
     const int dp = shadow_dp(D);
     float* xsr = xs + R.shadow;
 #pragma unroll

@@ -40,6 +40,12 @@ struct RepDev {
   double lnxi;      // log(xi), -inf for xi = 0
   double mw2;       // m omega^2 (trap)
   double inv_s2;    // 1/s^2 (0 if no pair term)
+  double inv_mp;    // 1/m' (bead mass)
+  double inv_q;     // 1/Q (thermostat mass)
+  double kT;        // 1/beta
+  double dt_mp;     // dt/m'
+  double trap_p;    // m omega^2 / P (trap force constant per bead)
+  float pair_k;     // sqrt(log2 e)/s, scale of the FP32 pair shadow (1 without pair term)
 };
 
 // Device pointers into the workspace (all replicas concatenated).
