@@ -9,5 +9,5 @@ from .wrapper import (  # noqa: F401
     OracleParams, OracleMD, lib_path, build, load,
     ring_energy, internal_energies, cycle_energies, forward_potentials,
     backward_potentials, connection_probabilities, exchange_forces, interaction,
-    compute_forces, step, conserved, density, exact_energy,
+    compute_forces, step, conserved, density, exact_energy, exact_energy_signed,
 )

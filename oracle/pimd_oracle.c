@@ -519,3 +519,39 @@ double oracle_exact_energy(int n, int dim, double beta, int p, double xi) {
     free(lnZ); free(EB); free(t);
     return out;
 }
+
+/* Linear-domain form of the same recursion for any real xi.  With
+ * zt(k) = z(kB) e^{d k B/2} = (1 - e^{-kB})^{-d} and Z_m = e^{-d m B/2} Zt_m:
+ *   Zt_m  = (1/m) sum_k xi^{k-1} zt(k) Zt_{m-k},            Zt_0 = 1,
+ *   Zt'_m = (1/m) sum_k xi^{k-1} (zt'(k) Zt_{m-k} + zt(k) Zt'_{m-k}),
+ *   zt'(k) = d zt/dB = -d k e^{-kB} (1 - e^{-kB})^{-d-1},
+ * and -d ln Z_n/dB = d n/2 - Zt'_n/Zt_n; E = (-d ln Z_n/dB) dB/dbeta.          */
+double oracle_exact_energy_signed(int n, int dim, double beta, int p, double xi) {
+    if (n < 1 || dim < 1 || !(beta > 0) || p < 0 || !isfinite(xi)) return NAN;
+    double B = beta, dB = 1.0;
+    if (p > 0) {
+        double a = 1.0 + beta * beta / (2.0 * (double)p * p);
+        B = (double)p * acosh(a);
+        dB = (beta / (double)p) / sqrt(a * a - 1.0);
+    }
+    double* Z = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    double* dZ = (double*)malloc(sizeof(double) * (size_t)(n + 1));
+    if (!Z || !dZ) { free(Z); free(dZ); return NAN; }
+    Z[0] = 1.0; dZ[0] = 0.0;
+    for (int m = 1; m <= n; ++m) {
+        double s = 0.0, ds = 0.0, xk = 1.0;   /* xk = xi^{k-1} */
+        for (int k = 1; k <= m; ++k) {
+            double q = exp(-(double)k * B);
+            double zt = pow(1.0 - q, -(double)dim);
+            double dzt = -(double)dim * (double)k * q * pow(1.0 - q, -(double)dim - 1.0);
+            s += xk * zt * Z[m - k];
+            ds += xk * (dzt * Z[m - k] + zt * dZ[m - k]);
+            xk *= xi;
+        }
+        Z[m] = s / (double)m;
+        dZ[m] = ds / (double)m;
+    }
+    double EB = 0.5 * (double)dim * (double)n - dZ[n] / Z[n];
+    free(Z); free(dZ);
+    return EB * dB;
+}

@@ -113,6 +113,13 @@ int oracle_density(const oracle_params* s, const double* x, int bins, double rma
  * for the P-bead discretisation (p >= 1) or the continuum (p = 0).           */
 double oracle_exact_energy(int n, int dim, double beta, int p, double xi);
 
+/* The same energy for any real xi, fermions (xi = -1) included, from the cycle
+ * recursion of the partition function written in the linear domain with signed
+ * terms: Z_m = (1/m) sum_k xi^{k-1} z(kB) Z_{m-k}.  The factors z(kB) are scaled
+ * by e^{d k B / 2} so that every term is O(1); intended for small n (the
+ * alternating sums of xi < 0 cancel increasingly with n).                    */
+double oracle_exact_energy_signed(int n, int dim, double beta, int p, double xi);
+
 #ifdef __cplusplus
 }
 #endif

@@ -112,6 +112,8 @@ def load():
         lib.oracle_conserved.argtypes = [P, C.POINTER(_MD), _dp, _dp, _dp, _dp]
         lib.oracle_exact_energy.restype = C.c_double
         lib.oracle_exact_energy.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double]
+        lib.oracle_exact_energy_signed.restype = C.c_double
+        lib.oracle_exact_energy_signed.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double]
         _lib = lib
     return _lib
 
@@ -249,3 +251,8 @@ def density(par: OracleParams, x, bins: int, rmax: float, counts=None) -> np.nda
 def exact_energy(n: int, dim: int, beta: float, p: int = 0, xi: float = 1.0) -> float:
     """Exact canonical energy of n free trapped particles (hbar = m = omega = 1); p = 0: continuum."""
     return load().oracle_exact_energy(n, dim, beta, p, xi)
+
+
+def exact_energy_signed(n: int, dim: int, beta: float, p: int = 0, xi: float = 1.0) -> float:
+    """The same for any real xi (fermions: xi = -1), linear-domain signed recursion; small n."""
+    return load().oracle_exact_energy_signed(n, dim, beta, p, xi)

@@ -28,6 +28,11 @@ MUTATIONS = {
     "virial half": ("ks_add(&vir, 0.5 * R(x, a, j, l) * gr);", "ks_add(&vir, R(x, a, j, l) * gr);"),
     "density binning": ("int b = (r >= rmax) ? bins : (int)(r / rmax * bins);",
                         "int b = (r >= rmax) ? bins : (int)(r * r / rmax * bins);"),
+    "signed recursion: xi power": ("            xk *= xi;\n", "            xk *= -xi;\n"),
+    "signed recursion: product rule": ("ds += xk * (dzt * Z[m - k] + zt * dZ[m - k]);",
+                                       "ds += xk * (dzt * Z[m - k]);"),
+    "signed recursion: ground-state shift": ("double EB = 0.5 * (double)dim * (double)n - dZ[n] / Z[n];",
+                                             "double EB = 0.5 * (double)dim - dZ[n] / Z[n];"),
 }
 
 
@@ -47,6 +52,7 @@ def test_pins_fail_on_planted_mistake(name):
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", lib, csrc, "-lm"])
         env = dict(os.environ, PIMD_ORACLE_LIB=lib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            "tests/test_oracle_pins.py", "tests/test_golden_paper.py"],
+                            "tests/test_oracle_pins.py", "tests/test_golden_paper.py",
+                            "tests/test_oracle_fermions.py"],
                            cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
