@@ -45,7 +45,19 @@ static int check_params(const oracle_params* s) {
     if (!(s->xi >= 0 && s->xi <= 1)) return -1;
     if (!(s->pair_amp >= 0)) return -1;
     if (s->pair_amp > 0 && !(s->pair_width > 0)) return -1;
+    if (s->n2 < 0 || s->n2 >= s->n) return -1;
     return 0;
+}
+
+/* Two species: particles 1..nA and nA+1..N (nA = N - n2).  A cycle [u,v] is allowed only
+ * within one species, and the 1/n factor of a block ending at particle v counts v within
+ * its species (the exchange sum of each species is its own Eq. 6).                    */
+static int species_a(const oracle_params* s) { return s->n - s->n2; }
+static int crosses(const oracle_params* s, int u, int v) {
+    return s->n2 > 0 && u <= species_a(s) && v > species_a(s);
+}
+static double local_index(const oracle_params* s, int v) {
+    return (double)(v > species_a(s) ? v - species_a(s) : v);
 }
 
 /* omega_P^2 = P / (beta hbar)^2  (Sec. III, after Eq. 7). */
@@ -152,9 +164,10 @@ int oracle_forward_potentials(const oracle_params* s, const double* E, double* X
     for (int n = 1; n <= N; ++n) {
         for (int k = 1; k <= n; ++k) {
             double e = E[(size_t)(n - k) * N + (n - 1)]; /* E^{[n-k+1,n]} */
-            t[k - 1] = log_xi_pow(s->xi, k - 1) - (s->beta * e + X[n - k]);
+            t[k - 1] = crosses(s, n - k + 1, n) ? -INFINITY
+                                                : log_xi_pow(s->xi, k - 1) - (s->beta * e + X[n - k]);
         }
-        X[n] = log((double)n) - log_sum_exp(t, n);
+        X[n] = log(local_index(s, n)) - log_sum_exp(t, n);
     }
     free(t);
     return 0;
@@ -174,7 +187,8 @@ int oracle_backward_potentials(const oracle_params* s, const double* E, double* 
         int cnt = 0;
         for (int l = u; l <= N; ++l) {
             double e = E[(size_t)(u - 1) * N + (l - 1)]; /* E^{[u,l]} */
-            t[cnt++] = log_xi_pow(s->xi, l - u) - log((double)l) - (s->beta * e + Y[l + 1]);
+            t[cnt++] = crosses(s, u, l) ? -INFINITY
+                                        : log_xi_pow(s->xi, l - u) - log(local_index(s, l)) - (s->beta * e + Y[l + 1]);
         }
         Y[u] = -log_sum_exp(t, cnt);
     }
@@ -195,10 +209,12 @@ int oracle_connection_probabilities(const oracle_params* s, const double* E,
         for (int lp = 1; lp <= N; ++lp) {
             double pr = 0.0;
             if (lp <= l) {
-                double e = E[(size_t)(lp - 1) * N + (l - 1)]; /* E^{[l',l]} */
-                double lw = log_xi_pow(s->xi, l - lp) - log((double)l);
-                pr = exp(lw - (X[lp - 1] + s->beta * e + Y[l + 1]) + XN);
-            } else if (lp == l + 1) {
+                if (!crosses(s, lp, l)) {
+                    double e = E[(size_t)(lp - 1) * N + (l - 1)]; /* E^{[l',l]} */
+                    double lw = log_xi_pow(s->xi, l - lp) - log(local_index(s, l));
+                    pr = exp(lw - (X[lp - 1] + s->beta * e + Y[l + 1]) + XN);
+                }
+            } else if (lp == l + 1 && !crosses(s, l, l + 1)) {
                 pr = 1.0 - exp(-(X[l] + Y[l + 1]) + XN);
             }
             G[(size_t)(l - 1) * N + (lp - 1)] = pr;

@@ -38,6 +38,10 @@ typedef struct {
     double xi;          /* exchange parameter, 0 <= xi <= 1 (Sec. II, Eq. 2)       */
     double pair_amp;    /* Gaussian pair amplitude A >= 0 (Eq. 20 with A = g/(pi s^2) or A = g) */
     double pair_width;  /* Gaussian width s > 0                                    */
+    int32_t n2;         /* particles of a second species (the last n2; 0 = one species,
+                           0 <= n2 < n): exchange cycles stay within a species, the
+                           1/n factors of Eqs. 6, 11, 12 count within the species, and the
+                           pair and trap terms act on all particles                 */
 } oracle_params;
 
 typedef struct {

@@ -36,7 +36,7 @@ class _Params(C.Structure):
     _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("dim", C.c_int32),
                 ("beta", C.c_double), ("hbar", C.c_double), ("mass", C.c_double),
                 ("omega", C.c_double), ("xi", C.c_double), ("pair_amp", C.c_double),
-                ("pair_width", C.c_double)]
+                ("pair_width", C.c_double), ("n2", C.c_int32)]
 
 
 class _Energies(C.Structure):
@@ -62,10 +62,11 @@ class OracleParams:
     hbar: float = 1.0
     mass: float = 1.0
     omega: float = 1.0
+    n2: int = 0          # particles of a second species (the last n2); 0 = one species
 
     def c(self) -> _Params:
         return _Params(self.n, self.p, self.dim, self.beta, self.hbar, self.mass,
-                       self.omega, self.xi, self.pair_amp, self.pair_width)
+                       self.omega, self.xi, self.pair_amp, self.pair_width, self.n2)
 
 
 @dataclass

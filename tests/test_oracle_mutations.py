@@ -10,14 +10,15 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 MUTATIONS = {
-    "drop 1/l in Eq. 12": ("double lw = log_xi_pow(s->xi, l - lp) - log((double)l);",
+    "drop 1/l in Eq. 12": ("double lw = log_xi_pow(s->xi, l - lp) - log(local_index(s, l));",
                            "double lw = log_xi_pow(s->xi, l - lp);"),
     "transposed Pr in Eq. 15": ("double g_in = G[(size_t)(lp - 1) * N + (l - 1)];",
                                 "double g_in = G[(size_t)(l - 1) * N + (lp - 1)];"),
-    "local index in Eq. 11": ("- log((double)l) - (s->beta * e + Y[l + 1]);",
+    "local index in Eq. 11": ("- log(local_index(s, l)) - (s->beta * e + Y[l + 1]);",
                               "- log((double)(l - u + 1)) - (s->beta * e + Y[l + 1]);"),
     "sign in Eq. 10": ("+ c * sqdist_beads(s, x, P, u, 1, u + 1)", "- c * sqdist_beads(s, x, P, u, 1, u + 1)"),
-    "xi power in Eq. 6": ("t[k - 1] = log_xi_pow(s->xi, k - 1)", "t[k - 1] = log_xi_pow(s->xi, k)"),
+    "xi power in Eq. 6": (": log_xi_pow(s->xi, k - 1) - (s->beta * e + X[n - k]);",
+                          ": log_xi_pow(s->xi, k) - (s->beta * e + X[n - k]);"),
     "pair force sign": ("g[(size_t)(l - 1) * D + a] += -2.0 * u * d * inv_s2;",
                         "g[(size_t)(l - 1) * D + a] += 2.0 * u * d * inv_s2;"),
     "bead index in Eq. 17": ("R(x, a, j + 1, l) - R(x, a, j - 1, l));", "R(x, a, j + 1, l) - R(x, a, j, l));"),
@@ -33,6 +34,12 @@ MUTATIONS = {
                                        "ds += xk * (dzt * Z[m - k]);"),
     "signed recursion: ground-state shift": ("double EB = 0.5 * (double)dim * (double)n - dZ[n] / Z[n];",
                                              "double EB = 0.5 * (double)dim - dZ[n] / Z[n];"),
+    "species: global 1/n": ("return (double)(v > species_a(s) ? v - species_a(s) : v);", "return (double)v;"),
+    "species: cycles across species": ("return s->n2 > 0 && u <= species_a(s) && v > species_a(s);",
+                                       "return s->n2 > 0 && u < species_a(s) && v > species_a(s) + 1;"),
+    "species: Pr across the boundary in Eq. 12": ("if (!crosses(s, lp, l)) {", "if (1) {"),
+    "species: boundary in Eq. 6": ("t[k - 1] = crosses(s, n - k + 1, n) ? -INFINITY",
+                                   "t[k - 1] = crosses(s, n - k, n) ? -INFINITY"),
 }
 
 
@@ -53,6 +60,6 @@ def test_pins_fail_on_planted_mistake(name):
         env = dict(os.environ, PIMD_ORACLE_LIB=lib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             "tests/test_oracle_pins.py", "tests/test_golden_paper.py",
-                            "tests/test_oracle_fermions.py"],
+                            "tests/test_oracle_fermions.py", "tests/test_oracle_species.py"],
                            cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
