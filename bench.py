@@ -78,11 +78,12 @@ def run_path(precision, R, steps, warmup, profile=False, knobs=None):
     return dt, systems, times
 
 
-def algorithmic_work(kind, systems, P, D):
+def algorithmic_work(kind, systems, P, D, precision="mixed"):
     """(bound, units per launch, work per unit, unit name, peak) for one kernel kind."""
     npairs = sum(P * s.n * (s.n - 1) // 2 for s in systems if s.pair_amp > 0)  # unordered pairs
     tri = sum(s.n * (s.n + 1) // 2 for s in systems)
     dofs = sum(D * P * s.n for s in systems)
+    parts = sum(s.n for s in systems)
     if kind == "pair":
         # per unordered pair (Eq. 20 counts each once): D subtractions, D FMAs (|dr|^2), one exp,
         # D FMAs for the force on each of the two particles = 7D + 1 flops (FMA = 2)
@@ -91,17 +92,24 @@ def algorithmic_work(kind, systems, P, D):
         # two recursions, each N(N+1)/2 terms; per term (FP64, FMA = 2): distance D + 2D, exponent 4,
         # table exp 17, sum 1, payload sums 2(D+1)  ->  5D + 24 flops
         return "alu", 2 * tri, 5 * D + 24, "TFLOP/s", PEAK_FP64_TFLOPS
-    if kind in ("springs",):
-        # read x, write f (8 B each per dof), plus end beads / links per particle (small)
-        return "hbm", dofs, 16, "GB/s", PEAK_HBM_GBS
+    if kind == "springs":
+        # per dof: read x, write f (8 B each), FP32 shadow (4 B, mixed); per particle: end beads,
+        # link and internal energy ((2D + 2) x 8 B), spread over its D P dofs
+        per = 16 + (4 if precision == "mixed" else 0) + (2 * D + 2) * 8 / (D * P)
+        return "hbm", dofs, per, "GB/s", PEAK_HBM_GBS
     if kind == "integrate_first":
-        # x, p, f, eta[4], veta[4] read; x, p, eta, veta written
+        # read x, p, f, eta[4], veta[4]; write x, p, eta[4], veta[4]
         return "hbm", dofs, 8 * (11 + 10), "GB/s", PEAK_HBM_GBS
     if kind == "integrate_second":
-        return "hbm", dofs, 8 * (11 + 9), "GB/s", PEAK_HBM_GBS
+        # read p, f, f_pair, eta[4], veta[4]; write p, f, eta[4], veta[4]
+        return "hbm", dofs, 8 * (11 + 10), "GB/s", PEAK_HBM_GBS
     if kind == "integrate_fused":
-        # read x, p, f, f_pair, eta[4], veta[4]; write x, p, f, eta[4], veta[4]
-        return "hbm", dofs, 8 * (12 + 11), "GB/s", PEAK_HBM_GBS
+        # read x, p, f, f_pair, eta[4], veta[4]; write x, p, eta[4], veta[4]
+        return "hbm", dofs, 8 * (12 + 10), "GB/s", PEAK_HBM_GBS
+    if kind == "exchange_forces":
+        # per particle: potentials and links (7), row averages (2D + 1), end beads and their
+        # neighbours (6D) read, bead 1 and bead P forces read and written (4D)  ->  (8 + 12D) x 8 B
+        return "hbm", parts, 8 * (8 + 12 * D), "GB/s", PEAK_HBM_GBS
     return "hbm", dofs, 8, "GB/s", PEAK_HBM_GBS
 
 
@@ -227,8 +235,15 @@ def main():
     avg_s = ms_total / max(launches, 1) / 1e3
     bound, units, per_unit, unit, peak = algorithmic_work(kind, systems, P, D)
     achieved = units * per_unit / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
-    kernels = {k: {"avg_us": v[0] / max(v[1], 1) * 1e3, "launches": v[1], "total_ms": v[0]}
-               for k, v in times.items() if v[1] > 0}
+    kernels = {}
+    for k, v in times.items():
+        if v[1] == 0:
+            continue
+        b, u, pu, un, pk = algorithmic_work(k, systems, P, D)
+        avg = v[0] / v[1] / 1e3
+        ach = u * pu / avg / (1e12 if un == "TFLOP/s" else 1e9)
+        kernels[k] = {"avg_us": avg * 1e6, "launches": v[1], "total_ms": v[0], "bound": b,
+                      "achieved": ach, "unit": un, "frac": ach / pk}
 
     rel = energy_precision_error()
     cpu = None if args.no_cpu_baseline else cpu_baseline()
