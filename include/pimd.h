@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define PIMD_ABI_VERSION 2
+#define PIMD_ABI_VERSION 3
 
 typedef enum {
     PIMD_OK = 0,
@@ -74,7 +74,13 @@ typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
  * hbar = m = omega = k_B = 1 (Sec. IV.A). */
 typedef struct {
     int32_t n;            /* particles, N >= 1                                               */
-    int32_t reserved;     /* must be 0                                                       */
+    int32_t n2;           /* particles of a second species, 0 <= n2 < n (0: one species).  The
+                             last n2 particles form it.  Sec. II treats one spin-polarised
+                             species and notes that coexisting spins follow directly: the
+                             exchange sum factorises over species, so exchange cycles (Eqs. 6-14)
+                             never join particles of different species, each species counts its
+                             own 1/n factors, and Pr[n - n2 -> n - n2 + 1] = 0.  The trap and the
+                             pair term act on all particles alike.                           */
     double beta;          /* inverse temperature > 0                                         */
     double hbar;          /* > 0                                                             */
     double mass;          /* particle mass m > 0; spring constant m omega_P^2, omega_P = sqrt(P)/(beta hbar) (Sec. III) */

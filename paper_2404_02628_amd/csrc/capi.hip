@@ -76,7 +76,7 @@ pimd_status validate(const pimd_config* c) {
     const pimd_replica& q = c->replicas[r];
     std::string where = "replica " + std::to_string(r) + ": ";
     if (q.n < 1 || q.n > (1 << 20)) return fail(PIMD_ERR_INVALID, where + "n must be in 1..2^20");
-    if (q.reserved != 0) return fail(PIMD_ERR_INVALID, where + "reserved must be 0");
+    if (q.n2 < 0 || q.n2 >= q.n) return fail(PIMD_ERR_INVALID, where + "n2 must be in 0..n-1");
     if (!(q.beta > 0) || !std::isfinite(q.beta)) return fail(PIMD_ERR_INVALID, where + "beta must be > 0");
     if (!(q.hbar > 0) || !std::isfinite(q.hbar)) return fail(PIMD_ERR_INVALID, where + "hbar must be > 0");
     if (!(q.mass > 0) || !std::isfinite(q.mass)) return fail(PIMD_ERR_INVALID, where + "mass must be > 0");
@@ -122,6 +122,7 @@ void make_plan(const pimd_config* c, Plan& pl) {
     R.npad = (int)round_up(q.n, kTile);
     R.npp = R.npad + kTile;
     R.nblk = (q.n + kTile - 1) / kTile;
+    R.na = q.n - q.n2;
     R.ndof = (long long)d.D * d.P * q.n;
     R.dof = G;
     G += round_up(R.ndof, 64);

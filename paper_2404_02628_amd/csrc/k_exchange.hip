@@ -17,6 +17,13 @@
 // so both are one lower-triangular log-sum-exp recursion whose terms need only end beads and
 // links: no prefix sums and no O(N^2) table.  V_xi^{[1,N]} = sum E_int + sum link - G^f_N/beta.
 //
+// Two species (particles 1..na and na+1..N).  The exchange sum factorises over species, so a
+// block [u,v] with u <= na < v never occurs and each 1/n factor counts within its species.  In
+// the recursion this is a boundary bnd (forward na, backward N - na): rows i > bnd only take
+// columns j >= bnd, the forward rho_i uses log(i - bnd) and the backward gamma_j uses
+// log(bnd - j) for j < bnd.  The link across the boundary is set to 0 (no allowed block holds
+// it), and Pr[na -> na+1] = 0.  With one species bnd = N forward and 0 backward: no mask.
+//
 // Probabilities without a G matrix.  Eq. 12 in this notation is a recursion term times a
 // factor of its row: Pr[n -> m+1] = exp(alpha^f_{n,m} + G^f_m) exp(G^b_{N-n} - G^f_N - beta link_n)
 // (forward row n) and Pr[l -> u] = exp(alpha^b_{i,j} + G^b_j) exp(G^f_{u-1} - G^f_N - beta
@@ -49,6 +56,7 @@ template <int D>
 struct RecMap {
   const double* a; const double* b; const double* lk;
   int N, npp, dir;
+  int bnd;   // species boundary in this direction's row numbering
   double beta;
   // end point p_i and the link value entering rho_i, for 1 <= i <= N
   __device__ inline void row_load(int i, double (&pt)[D], double& lv) const {
@@ -63,7 +71,7 @@ struct RecMap {
     }
   }
   __device__ inline double row_rho(int i, double lv) const {
-    return dir == 0 ? beta * lv - log((double)i) : beta * lv;
+    return dir == 0 ? beta * lv - log((double)(i > bnd ? i - bnd : i)) : beta * lv;
   }
   // column point q_j, for 0 <= j <= N-1
   __device__ inline void col_load(int j, double (&q)[D]) const {
@@ -75,7 +83,9 @@ struct RecMap {
       for (int c = 0; c < D; ++c) q[c] = b[(long long)c * npp + (N - j - 1)];
     }
   }
-  __device__ inline double col_gamma(int j) const { return dir == 0 ? 0.0 : -log((double)(N - j)); }
+  __device__ inline double col_gamma(int j) const {
+    return dir == 0 ? 0.0 : -log((double)(j < bnd ? bnd - j : N - j));
+  }
 };
 
 // Waves per recursion workgroup: the cooperative chain kernel uses eight (its block latency is
@@ -247,10 +257,10 @@ __device__ inline void write_avg(const SH& sh, const RowCarry<D>& cy, double* __
 }
 
 // (2a) in-block coefficients alpha_{i,j} (without G_j) from the staged column records; each wave
-// fills its eight columns.
+// fills its columns.  Blocks across the species boundary are masked (-inf).
 template <int D, class SH>
 __device__ inline void inblock_alpha(SH& sh, int cur, int blk, int i, const double (&pi)[D], double rho,
-                                     bool valid, double bc, double lnxi) {
+                                     bool valid, double bc, double lnxi, int bnd) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int u = 0; u < SH::kCols; ++u) {
@@ -262,7 +272,7 @@ __device__ inline void inblock_alpha(SH& sh, int cur, int blk, int i, const doub
 #pragma unroll
     for (int c = 0; c < D; ++c) { const double t = pi[c] - qv[c]; d2 = fma(t, t, d2); }
     const double v = xi_pow_log(i - 1 - j, lnxi) + rho + r4.w - bc * d2;
-    sh.Am[sc * kTile + lane] = (valid && j < i) ? v : -INFINITY;
+    sh.Am[sc * kTile + lane] = (valid && j < i && (i <= bnd || j >= bnd)) ? v : -INFINITY;
   }
 }
 
@@ -469,6 +479,7 @@ __device__ inline RecMap<D> rec_map(const RepDev& R, const double* ends, const d
   mp.b = mp.a + (long long)D * R.npp;
   mp.lk = link + R.part;
   mp.N = R.n; mp.npp = R.npp; mp.dir = dir; mp.beta = R.beta;
+  mp.bnd = dir == 0 ? R.na : R.n - R.na;
   return mp;
 }
 
@@ -530,12 +541,16 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
     if (blk + 1 < nblk) pf.load(mp, blk + 1, wave == 0);
     const RowCtx rc{i, rho, bc, lnxi};
     const int jend = blk * kTile;
+    // earlier columns this block's rows may take: [jlo, jend); in the block across the species
+    // boundary the rows of the second species take none of them
+    const int jlo = jend > mp.bnd ? mp.bnd : 0;
+    const bool bulk_ok = valid && (i <= mp.bnd || jlo == mp.bnd);
 
     // (0) reference: largest term among the previous block's columns
     double Rref = 0.0;
     if (jend > 0) {
       double mx = -INFINITY;
-      if (valid) {
+      if (bulk_ok) {
         const double4* cp = sh.col[cur ^ 1];
         const int j0 = wave * kBatchCols;
 #pragma unroll
@@ -547,6 +562,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
           if (xm == kXiOne) t = term_of<D, kXiOne>(rc, pi, r4, j, d2);
           else if (xm == kXiZero) t = term_of<D, kXiZero>(rc, pi, r4, j, d2);
           else t = term_of<D, kXiGen>(rc, pi, r4, j, d2);
+          if (j < jlo) t = -INFINITY;
           mx = fmax(mx, t);
         }
       }
@@ -563,9 +579,9 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
     double m = -1e300, s = 0.0, P[D + 1];
 #pragma unroll
     for (int q = 0; q <= D; ++q) P[q] = 0.0;
-    if (valid && jend > 0) {
-      const int per = (jend + kBatchWaves - 1) / kBatchWaves;
-      const int ja = min(jend, wave * per), jb = min(jend, ja + per);
+    if (bulk_ok && jend > jlo) {
+      const int per = (jend - jlo + kBatchWaves - 1) / kBatchWaves;
+      const int ja = min(jend, jlo + wave * per), jb = min(jend, ja + per);
       if (xm == kXiOne) bulk_rows<D, kXiOne>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
       else if (xm == kXiZero) bulk_rows<D, kXiZero>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
       else bulk_rows<D, kXiGen>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
@@ -574,7 +590,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
     sh.ps[wave][lane] = s;
 #pragma unroll
     for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = P[q];
-    inblock_alpha<D>(sh, cur, blk, i, pi, rho, valid, bc, lnxi);
+    inblock_alpha<D>(sh, cur, blk, i, pi, rho, valid, bc, lnxi, mp.bnd);
     const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
     solve_block<D>(sh, blk, cur, N, valid, rec, G, av, npp, pi, cn, nullptr, 0, cy, [] {});
   }
@@ -704,15 +720,21 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
       const double rho = valid ? mp.row_rho(i, pf.lv) : 0.0;
       if (blk + 1 < nblk) pf.load(mp, blk + 1, wave == 0);
       const RowCtx rc{i, rho, bc, lnxi};
-      inblock_alpha<D>(sh, cur, blk, i, pi, rho, valid, bc, lnxi);
+      inblock_alpha<D>(sh, cur, blk, i, pi, rho, valid, bc, lnxi, mp.bnd);
       double m = -1e300, s = 0.0, P[D + 1];
 #pragma unroll
       for (int q = 0; q <= D; ++q) P[q] = 0.0;
+      // earlier columns these rows may take: [jlo, blk*64) (species boundary, as in k_recursion)
+      const int jlo = blk * kTile > mp.bnd ? mp.bnd : 0;
+      const bool bulk_ok = valid && (i <= mp.bnd || jlo == mp.bnd);
       // the panel just finished (columns of block blk-1, in LDS), one 8-column slice per wave
-      if (blk >= 1 && valid)
-        fold_any<D, kCoopCols>(xm, rc, pi, sh.col[cur ^ 1] + wave * kCoopCols, (blk - 1) * kTile + wave * kCoopCols,
-                    kCoopCols, sh.tab, m, s, P);
-      if (have_part && hs > 0.0) {
+      if (blk >= 1 && bulk_ok) {
+        const int j0 = (blk - 1) * kTile + wave * kCoopCols, js = max(j0, jlo);
+        if (js < j0 + kCoopCols)
+          fold_any<D, kCoopCols>(xm, rc, pi, sh.col[cur ^ 1] + wave * kCoopCols + (js - j0), js,
+                                 j0 + kCoopCols - js, sh.tab, m, s, P);
+      }
+      if (bulk_ok && have_part && hs > 0.0) {
         const double M = fmax(m, hm);
         const double f0 = fast_exp(m - M, sh.tab), f1 = fast_exp(hm - M, sh.tab);
         s = s * f0 + hs * f1;
@@ -761,10 +783,12 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
     if (valid) mp.row_load(i, pi, lv);
     const double rho = valid ? mp.row_rho(i, lv) : 0.0;
     const RowCtx rc{i, rho, bc, lnxi};
+    const int jlo = blk * kTile > mp.bnd ? mp.bnd : 0;
+    const bool bulk_ok = valid && (i <= mp.bnd || jlo == mp.bnd);
     double m = -1e300, s = 0.0, P[D + 1];
 #pragma unroll
     for (int q = 0; q <= D; ++q) P[q] = 0.0;
-    for (int c = 0; c <= blk - 2; ++c) {
+    for (int c = jlo / kTile; c <= blk - 2; ++c) {
       if (c > ready) {
         if (threadIdx.x == 0) {
           int r = wait_epoch(panel_ready + c, epoch, err) ? c : -2;
@@ -780,10 +804,9 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
         __syncthreads();
         if (ready < 0) return;   // a wait failed: the error word is raised, stop this helper
       }
-      if (valid) {
-        const int j0 = c * kTile + wave * kCoopCols;
-        fold_any<D, kCoopCols>(xm, rc, pi, rec + j0, j0, kCoopCols, sh.tab, m, s, P);
-      }
+      const int j0 = c * kTile + wave * kCoopCols, js = max(j0, jlo);
+      if (bulk_ok && js < j0 + kCoopCols)
+        fold_any<D, kCoopCols>(xm, rc, pi, rec + js, js, j0 + kCoopCols - js, sh.tab, m, s, P);
     }
     sh.pm[wave][lane] = m;
     sh.ps[wave][lane] = s;
@@ -867,22 +890,27 @@ int recursion_coop_max_blocks_per_cu(int D) {
 // ------------------------------------------------------------------ probabilities
 
 // Pr[l -> l'] for 0-based particles lr >= lc (entry of Eq. 12 in normalised form).
+// Zero for a block across the species boundary (lc < na <= lr).
 template <int D>
-__device__ inline double prob_lower(int lr, int lc, int N, const double* a, const double* b, int npp,
+__device__ inline double prob_lower(int lr, int lc, int N, int na, const double* a, const double* b, int npp,
                                     const double* gf, const double* gb, double bc, double lnxi) {
+  if (lc < na && lr >= na) return 0.0;
   double d2 = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     double t = b[(long long)c * npp + lr] - a[(long long)c * npp + lc];
     d2 = fma(t, t, d2);
   }
-  double ex = xi_pow_log(lr - lc, lnxi) - log((double)(lr + 1)) + gf[lc] + gb[N - 1 - lr] - gf[N] - bc * d2;
+  const int loc = lr >= na ? lr + 1 - na : lr + 1;   // 1/l counts within the species
+  double ex = xi_pow_log(lr - lc, lnxi) - log((double)loc) + gf[lc] + gb[N - 1 - lr] - gf[N] - bc * d2;
   return exp(ex);
 }
 
-// Pr[l -> l+1] for 0-based l <= N-2 (Eq. 13 in normalised form), 0 for l = N-1.
-__device__ inline double prob_next(int l, int N, const double* lk, const double* gf, const double* gb, double beta) {
-  if (l >= N - 1) return 0.0;
+// Pr[l -> l+1] for 0-based l <= N-2 (Eq. 13 in normalised form), 0 for the last particle of
+// each species (l = na-1, l = N-1).
+__device__ inline double prob_next(int l, int N, int na, const double* lk, const double* gf, const double* gb,
+                                   double beta) {
+  if (l >= N - 1 || l == na - 1) return 0.0;
   return -expm1(gf[l + 1] + gb[N - 1 - l] - gf[N] - beta * lk[l]);
 }
 
@@ -919,8 +947,8 @@ __global__ __launch_bounds__(256) void k_probs_reduce(const RepDev* __restrict__
     const double* avb = avf + (long long)(D + 1) * npp;
     const double w_end = exp(g_f[l + 1] + g_b[N - 1 - l] - g_f[N] - R.beta * lk[l]);
     const double w_start = exp(g_b[N - l] + g_f[l] - g_f[N] - (l > 0 ? R.beta * lk[l - 1] : 0.0));
-    const double pn = prob_next(l, N, lk, g_f, g_b, R.beta);                          // Pr[L -> L+1]
-    const double pp = (l > 0) ? prob_next(l - 1, N, lk, g_f, g_b, R.beta) : 0.0;        // Pr[L-1 -> L]
+    const double pn = prob_next(l, N, R.na, lk, g_f, g_b, R.beta);                    // Pr[L -> L+1]
+    const double pp = (l > 0) ? prob_next(l - 1, N, R.na, lk, g_f, g_b, R.beta) : 0.0;  // Pr[L-1 -> L]
     const double rs = w_end + pn, cs = w_start + pp;
     const double kap = R.kappa;
     double* fr = f + R.dof;
@@ -1010,8 +1038,8 @@ __global__ void k_debug_probs(const RepDev* __restrict__ reps, int r, int row0, 
   const double* a = ends + 2LL * D * R.part;
   const double* b = a + (long long)D * R.npp;
   double v = 0.0;
-  if (lc <= lr) v = prob_lower<D>(lr, lc, N, a, b, R.npp, gf + R.part, gb + R.part, R.beta * R.c, R.lnxi);
-  else if (lc == lr + 1) v = prob_next(lr, N, link + R.part, gf + R.part, gb + R.part, R.beta);
+  if (lc <= lr) v = prob_lower<D>(lr, lc, N, R.na, a, b, R.npp, gf + R.part, gb + R.part, R.beta * R.c, R.lnxi);
+  else if (lc == lr + 1) v = prob_next(lr, N, R.na, link + R.part, gf + R.part, gb + R.part, R.beta);
   G[idx] = v;
 }
 

@@ -5,6 +5,7 @@
 //   * trap forces             -(1/P) m omega^2 r^j on every bead                      (Eqs. 4, 19)
 //   * E_int^{(l)} = (1/2) m omega_P^2 sum_{j<P} |r^{j+1} - r^j|^2                       (Eq. 9)
 //   * link_l = (1/2) m omega_P^2 |r_l^P - r_{l+1}^1|^2 (the inter-ring term of Eq. 7), 0 for l = N
+//     and for the last particle of the first species (no allowed cycle contains that link)
 //   * the end beads r_l^1, r_l^P used by the exchange recursion (Eqs. 6-16)
 //   * in mixed precision, the FP32 shadow of the positions for the pair kernel, stored
 //     slice-major [P][N][dp] and pre-scaled by sqrt(log2 e)/s so the pair kernel evaluates
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restri
       ut += rc * rc;
       if (SHADOW) xsr[((long long)(P - 1) * R.npad + l) * dp + a] = (float)rc * kscale;
       b_out[(long long)a * R.npp + l] = rc;
-      if (l + 1 < N) {
+      if (l + 1 < N && l + 1 != R.na) {
         double dl = rc - xa[l + 1];
         lk += dl * dl;
       }
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restri
     lk *= R.c;
     ut *= 0.5 * R.mw2;
     eint[R.part + l] = e_int;
-    link[R.part + l] = lk;   // zero for the last particle
+    link[R.part + l] = lk;   // zero for the last particle of each species
     acc[0] = e_int; acc[1] = lk; acc[2] = ut;
   }
   block_sum<3>(acc, lds);

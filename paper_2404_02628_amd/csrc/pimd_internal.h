@@ -27,6 +27,7 @@ struct RepDev {
   int npad;         // N rounded up to kTile
   int npp;          // per-replica stride of particle arrays (npad + kTile, holds N+1 entries)
   int nblk;         // ceil(N / kTile)
+  int na;           // particles of the first species (N - n2): cycles never join l <= na and l > na
   long long dof;    // offset of this replica's x, p, f, fpair block ([dim][P][N], contiguous)
   long long ndof;   // dim * P * N
   long long part;   // offset unit for particle arrays (sum of npp of earlier replicas)
@@ -55,7 +56,7 @@ struct DevPtrs {
   float* xs;                   // FP32 shadow of x for the pair kernel, layout per replica [P][npad][dp]
   double* eta; double* veta;   // [M][G]
   double* ends;                // per replica: [2*dim][npp]  (a = first beads, then b = last beads)
-  double* link;                // [npp]: c |b_l - a_{l+1}|^2, 0 for the last particle
+  double* link;                // [npp]: c |b_l - a_{l+1}|^2, 0 for the last particle of each species
   double* eint;                // [npp]: internal spring energy of each ring
   double* gf; double* gb;      // [npp]: forward / backward normalised log-potentials, rows 0..N
   double4* colrec;             // [2][npp] per replica: recursion column records {q_j, colc_j + G_j}

@@ -36,7 +36,7 @@ EXPORTED = [
 
 
 class pimd_replica(C.Structure):
-    _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("beta", C.c_double), ("hbar", C.c_double),
+    _fields_ = [("n", C.c_int32), ("n2", C.c_int32), ("beta", C.c_double), ("hbar", C.c_double),
                 ("mass", C.c_double), ("omega", C.c_double), ("xi", C.c_double), ("pair_amp", C.c_double),
                 ("pair_width", C.c_double), ("dt", C.c_double), ("nhc_q", C.c_double), ("bead_mass", C.c_double)]
 
@@ -260,7 +260,7 @@ class Context:
         self.bins = density_bins
         reps = (pimd_replica * len(systems))()
         for k, s in enumerate(systems):
-            reps[k] = pimd_replica(s.n, 0, s.beta, s.hbar, s.mass, s.omega, s.xi, s.pair_amp,
+            reps[k] = pimd_replica(s.n, s.n2, s.beta, s.hbar, s.mass, s.omega, s.xi, s.pair_amp,
                                    s.pair_width if s.pair_amp > 0 else 1.0, s.dt, 0.0, s.bead_mass)
         self._reps = reps
         m = systems[0].nhc_len if nhc_len is None else nhc_len

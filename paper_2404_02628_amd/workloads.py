@@ -43,6 +43,7 @@ class System:
     dt: float = 0.01
     nhc_len: int = 4
     bead_mass: float = 0.0   # <= 0: the particle mass
+    n2: int = 0              # particles of a second species (the last n2); exchange stays within a species
 
     def with_(self, **kw) -> "System":
         return replace(self, **kw)

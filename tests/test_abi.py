@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(lib):
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
     assert set(names) == set(lib.EXPORTED)
-    assert lib.pimd_abi_version() == 2
+    assert lib.pimd_abi_version() == 3
 
 
 def _cfg(lib, **over):
@@ -65,7 +65,7 @@ def test_workspace_size_is_positive_and_monotone(lib):
     {"recursion_workgroups": -1}, {"flags": 4}, {"flags": -1},
     {"rep": {"n": 0}}, {"rep": {"xi": -0.1}}, {"rep": {"xi": 1.5}}, {"rep": {"beta": 0.0}},
     {"rep": {"pair_amp": -1.0}}, {"rep": {"pair_amp": 1.0, "pair_width": 0.0}}, {"rep": {"dt": 0.0}},
-    {"rep": {"reserved": 3}}, {"rep": {"mass": -1.0}},
+    {"rep": {"n2": -1}}, {"rep": {"n2": 37}}, {"rep": {"n2": 65}}, {"rep": {"mass": -1.0}},
 ])
 def test_invalid_configs_are_rejected(lib, over):
     cfg, _keep = _cfg(lib, **over)

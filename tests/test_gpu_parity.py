@@ -32,7 +32,7 @@ pytestmark = pytest.mark.gpu
 
 def oracle_params(orc, s):
     return orc.OracleParams(n=s.n, p=s.p, dim=s.dim, beta=s.beta, xi=s.xi, pair_amp=s.pair_amp,
-                            pair_width=s.pair_width, hbar=s.hbar, mass=s.mass, omega=s.omega)
+                            pair_width=s.pair_width, hbar=s.hbar, mass=s.mass, omega=s.omega, n2=s.n2)
 
 
 def rel_max(a, b):
