@@ -223,6 +223,17 @@ pimd_status pimd_debug_potentials(pimd_ctx* ctx, int32_t r, double* X, double* Y
  * Intended for tests at small N; recomputes the entries.  Synchronises. */
 pimd_status pimd_debug_probs(pimd_ctx* ctx, int32_t r, double* G);
 
+/* Cycle energies of replica r by their definition (Eq. 7), every entry evaluated
+ * on its own from the current positions: E[(u-1)*N + (v-1)] = E^{[u,v]} for
+ * u <= v and 0 for u > v (host array of N*N doubles).  This is the O(N^3 P)
+ * original algorithm of Sec. III; the force path never forms this table (its
+ * recursions regroup E into per-particle terms), so it serves as an
+ * independent cross-check and as a cost reference.  If ms is not NULL it
+ * receives the summed device time of the kernel launches (HIP events on the
+ * context's stream), copies excluded.  PIMD_ERR_STATE before any
+ * pimd_set_state.  Synchronises. */
+pimd_status pimd_cycle_energies(pimd_ctx* ctx, int32_t r, double* E, double* ms);
+
 /* Per-kernel timing with HIP events on the stream each kernel is launched
  * on.  pimd_profile(ctx, 1) clears and enables, 0 disables.  pimd_kernel_times
  * synchronises and writes, for up to max_kinds kernel kinds, the summed

@@ -56,6 +56,12 @@ enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LI
            S_SPRINGP, S_PAIRP, S_REDP, S_REC, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_SPRINGW, S_PAIRW, S_INTW, S_DBG,
            S_COUNT };
 
+// Doubles of the debug scratch: two potential arrays, or up to 2^20 entries of a dense N x N
+// table (filled in row chunks).
+long long dbg_doubles(int maxn) {
+  return std::max<long long>(2LL * (maxn + 2), std::min<long long>((long long)maxn * maxn, 1LL << 20));
+}
+
 pimd_status validate(const pimd_config* c) {
   if (!c) return fail(PIMD_ERR_INVALID, "config is NULL");
   if (c->n_replicas < 1) return fail(PIMD_ERR_INVALID, "n_replicas must be >= 1");
@@ -187,7 +193,7 @@ void make_plan(const pimd_config* c, Plan& pl) {
   sz[S_SPRINGW] = sizeof(int4) * d.nspringwg;
   sz[S_PAIRW] = sizeof(int4) * std::max<long long>(d.npairwork, 1);
   sz[S_INTW] = sizeof(int4) * d.nintwg;
-  sz[S_DBG] = 8ull * std::max<long long>(2LL * (maxn + 2), std::min<long long>((long long)maxn * maxn, 1LL << 20));
+  sz[S_DBG] = 8ull * dbg_doubles(maxn);
   size_t o = 0;
   for (int s = 0; s < S_COUNT; ++s) {
     pl.off[s] = o;
@@ -206,6 +212,7 @@ struct pimd_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool forces_valid = false;
   bool evaluated = false;
+  bool has_state = false;   // some replica's positions were set
   long long step = 0;
   bool has_pair = false;
   int helpers = 0;       // helper workgroups per recursion chain (0: one workgroup per chain)
@@ -501,6 +508,7 @@ pimd_status pimd_set_state(pimd_ctx* c, int32_t r, const double* x, const double
   }
   HIPCHK(hipStreamSynchronize(c->s));
   c->forces_valid = false;
+  c->has_state = true;
   return PIMD_OK;
 }
 
@@ -680,8 +688,7 @@ pimd_status pimd_debug_probs(pimd_ctx* c, int32_t r, double* G) {
   if (!G) return fail(PIMD_ERR_INVALID, "NULL output");
   if (!c->forces_valid) return fail(PIMD_ERR_STATE, "no force evaluation since the last set_state");
   const long long N = c->pl.reps[r].n;
-  const long long cap = std::max<long long>(2LL * (c->pl.d.maxn + 2), std::min<long long>((long long)c->pl.d.maxn * c->pl.d.maxn, 1LL << 20));
-  const long long rows = std::max<long long>(1, cap / N);
+  const long long rows = std::max<long long>(1, dbg_doubles(c->pl.d.maxn) / N);
   for (long long r0 = 0; r0 < N; r0 += rows) {
     const long long nr = std::min(rows, N - r0);
     HIPCHK(launch_debug_probs(c->pl.d, c->w, r, (int)N, (int)r0, (int)nr, c->w.dbg, c->s));
@@ -689,6 +696,37 @@ pimd_status pimd_debug_probs(pimd_ctx* c, int32_t r, double* G) {
     HIPCHK(hipStreamSynchronize(c->s));
   }
   return PIMD_OK;
+}
+
+pimd_status pimd_cycle_energies(pimd_ctx* c, int32_t r, double* E, double* ms) {
+  pimd_status st = check_ctx_r(c, r);
+  if (st != PIMD_OK) return st;
+  if (!E) return fail(PIMD_ERR_INVALID, "NULL output");
+  if (!c->has_state) return fail(PIMD_ERR_STATE, "no state set");
+  const long long N = c->pl.reps[r].n;
+  const long long rows = std::max<long long>(1, dbg_doubles(c->pl.d.maxn) / N);
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  if (!e0 || !e1) return fail(PIMD_ERR_DEVICE, "hipEventCreate failed");
+  auto run = [&]() -> pimd_status {
+    double total = 0.0;
+    for (long long r0 = 0; r0 < N; r0 += rows) {
+      const long long nr = std::min(rows, N - r0);
+      HIPCHK(hipEventRecord(e0, c->s));
+      HIPCHK(launch_cycle_direct(c->pl.d, c->w, r, (int)N, (int)r0, (int)nr, c->w.dbg, c->s));
+      HIPCHK(hipEventRecord(e1, c->s));
+      HIPCHK(hipMemcpyAsync(E + r0 * N, c->w.dbg, sizeof(double) * nr * N, hipMemcpyDeviceToHost, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      total += t;
+    }
+    if (ms) *ms = total;
+    return PIMD_OK;
+  };
+  st = run();
+  c->ev_pool.push_back(e0);
+  c->ev_pool.push_back(e1);
+  return st;
 }
 
 pimd_status pimd_profile(pimd_ctx* c, int enable) {

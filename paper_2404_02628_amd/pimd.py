@@ -31,7 +31,7 @@ EXPORTED = [
     "pimd_set_state", "pimd_get_state", "pimd_compute_forces", "pimd_get_forces", "pimd_step",
     "pimd_energies", "pimd_trace", "pimd_density", "pimd_reset_accumulators", "pimd_debug_potentials",
     "pimd_debug_probs", "pimd_profile", "pimd_kernel_times", "pimd_kernel_name", "pimd_synchronize",
-    "pimd_graph_info",
+    "pimd_graph_info", "pimd_cycle_energies",
 ]
 
 
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
         "pimd_kernel_name": (C.c_char_p, [C.c_int32]),
         "pimd_synchronize": (C.c_int, [_vp]),
         "pimd_graph_info": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+        "pimd_cycle_energies": (C.c_int, [_vp, C.c_int32, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -208,6 +209,14 @@ def pimd_debug_probs(h, r: int, n: int) -> np.ndarray:
     G = np.zeros((n, n))
     _chk(load().pimd_debug_probs(h, r, G.ctypes.data_as(_dp)), "pimd_debug_probs")
     return G
+
+
+def pimd_cycle_energies(h, r: int, n: int):
+    """(E, ms): the N x N table E^{[u,v]} evaluated entry by entry, and its kernel time."""
+    E = np.zeros((n, n))
+    ms = C.c_double()
+    _chk(load().pimd_cycle_energies(h, r, E.ctypes.data_as(_dp), C.byref(ms)), "pimd_cycle_energies")
+    return E, ms.value
 
 
 def pimd_profile(h, enable: bool):
@@ -324,6 +333,9 @@ class Context:
 
     def probabilities(self, r: int) -> np.ndarray:
         return pimd_debug_probs(self.h, r, self.systems[r].n)
+
+    def cycle_energies(self, r: int):
+        return pimd_cycle_energies(self.h, r, self.systems[r].n)
 
     def profile(self, on: bool):
         pimd_profile(self.h, on)
