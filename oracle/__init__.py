@@ -10,4 +10,5 @@ from .wrapper import (  # noqa: F401
     ring_energy, internal_energies, cycle_energies, forward_potentials,
     backward_potentials, connection_probabilities, exchange_forces, interaction,
     compute_forces, step, conserved, density, exact_energy, exact_energy_signed,
+    philox4x32_10, init_state,
 )

@@ -571,3 +571,58 @@ double oracle_exact_energy_signed(int n, int dim, double beta, int p, double xi)
     free(Z); free(dZ);
     return EB * dB;
 }
+
+/* ------------------------------------------------------------------ seeded initial state */
+
+/* One Philox round on (c0, c1, c2, c3) with round key (k0, k1): the products
+ * M0 c0 and M1 c2 are split into high and low words, and
+ * (c0, c1, c2, c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 53 random bits from two words, centred in (0, 1). */
+static double unit_open(uint32_t hi, uint32_t lo) {
+    uint64_t m = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+    return ((double)m + 0.5) * 0x1p-53;
+}
+
+/* Deviate e of array a (Box and Muller, Ann. Math. Stat. 29, 610 (1958)). */
+static double normal_deviate(uint64_t seed, uint32_t a, uint64_t e) {
+    uint64_t k = e >> 1;
+    uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), a, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    double u1 = unit_open(w[1], w[0]);
+    double u2 = unit_open(w[3], w[2]);
+    double rad = sqrt(-2.0 * log(u1));
+    double th = 6.283185307179586476925286766559 * u2;   /* 2 pi u2 */
+    return (e & 1) ? rad * sin(th) : rad * cos(th);
+}
+
+int oracle_init_state(const oracle_params* s, const oracle_md* md, double sigma, uint64_t seed,
+                      double* x, double* p) {
+    if (check_params(s) || !md || !(sigma >= 0) || !x || !p) return -1;
+    const double mp = md->bead_mass > 0 ? md->bead_mass : s->mass;
+    const double sp = sqrt(mp / s->beta);
+    const uint64_t n = (uint64_t)s->dim * (uint64_t)s->p * (uint64_t)s->n;
+    for (uint64_t e = 0; e < n; ++e) {
+        x[e] = sigma * normal_deviate(seed, 0u, e);
+        p[e] = sp * normal_deviate(seed, 1u, e);
+    }
+    return 0;
+}

@@ -124,6 +124,22 @@ double oracle_exact_energy(int n, int dim, double beta, int p, double xi);
  * alternating sums of xi < 0 cancel increasingly with n).                    */
 double oracle_exact_energy_signed(int n, int dim, double beta, int p, double xi);
 
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror and Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3", SC11): ten rounds of two 32x32->64
+ * multiplications (multipliers 0xD2511F53, 0xCD9E8D57) on the counter, with the
+ * key bumped by the Weyl constants 0x9E3779B9, 0xBB67AE85 between rounds.      */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Seeded initial state: x iid N(0, sigma^2) and p iid N(0, m'/beta) per coordinate
+ * (Maxwell-Boltzmann at beta for the bead mass m' of md).  Element e of array a
+ * (a = 0 positions, a = 1 momenta; e in the [dim][P][N] order) is deviate e mod 2
+ * of the Box-Muller pair k = e/2: Philox4x32-10 with counter {k mod 2^32,
+ * k / 2^32, a, 0} and key {seed mod 2^32, seed / 2^32} gives words w0..w3;
+ * u1 = ((w1 * 2^21 + w0 / 2^11) + 1/2) 2^-53, u2 likewise from w3, w2;
+ * deviates sqrt(-2 ln u1) cos(2 pi u2) and sqrt(-2 ln u1) sin(2 pi u2).          */
+int oracle_init_state(const oracle_params* s, const oracle_md* md, double sigma, uint64_t seed,
+                      double* x, double* p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,10 @@ def load():
         lib.oracle_exact_energy.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double]
         lib.oracle_exact_energy_signed.restype = C.c_double
         lib.oracle_exact_energy_signed.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double]
+        lib.oracle_philox4x32_10.restype = None
+        lib.oracle_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        lib.oracle_init_state.restype = C.c_int
+        lib.oracle_init_state.argtypes = [P, C.POINTER(_MD), C.c_double, C.c_uint64, _dp, _dp]
         _lib = lib
     return _lib
 
@@ -257,3 +261,21 @@ def exact_energy(n: int, dim: int, beta: float, p: int = 0, xi: float = 1.0) -> 
 def exact_energy_signed(n: int, dim: int, beta: float, p: int = 0, xi: float = 1.0) -> float:
     """The same for any real xi (fermions: xi = -1), linear-domain signed recursion; small n."""
     return load().oracle_exact_energy_signed(n, dim, beta, p, xi)
+
+
+def philox4x32_10(ctr, key) -> tuple:
+    """Philox4x32-10 of a 4-word counter and a 2-word key (four 32-bit words)."""
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    out = (C.c_uint32 * 4)()
+    load().oracle_philox4x32_10(c, k, out)
+    return tuple(out)
+
+
+def init_state(par: OracleParams, md: OracleMD, sigma: float, seed: int):
+    """(x, p): seeded positions N(0, sigma^2) and momenta N(0, m'/beta), layout (dim, P, N)."""
+    x = np.zeros((par.dim, par.p, par.n))
+    p = np.zeros_like(x)
+    _check(load().oracle_init_state(C.byref(par.c()), C.byref(md.c()), C.c_double(sigma), C.c_uint64(seed),
+                                    _ptr(x), _ptr(p)), "init_state")
+    return x, p

@@ -40,6 +40,9 @@ MUTATIONS = {
     "species: Pr across the boundary in Eq. 12": ("if (!crosses(s, lp, l)) {", "if (1) {"),
     "species: boundary in Eq. 6": ("t[k - 1] = crosses(s, n - k + 1, n) ? -INFINITY",
                                    "t[k - 1] = crosses(s, n - k, n) ? -INFINITY"),
+    "philox round count": ("for (int round = 0; round < 10; ++round) {", "for (int round = 0; round < 9; ++round) {"),
+    "philox word order": ("uint32_t n1 = (uint32_t)p1;", "uint32_t n1 = (uint32_t)p0;"),
+    "Box-Muller radius": ("double rad = sqrt(-2.0 * log(u1));", "double rad = sqrt(-log(u1));"),
 }
 
 
@@ -60,6 +63,7 @@ def test_pins_fail_on_planted_mistake(name):
         env = dict(os.environ, PIMD_ORACLE_LIB=lib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             "tests/test_oracle_pins.py", "tests/test_golden_paper.py",
-                            "tests/test_oracle_fermions.py", "tests/test_oracle_species.py"],
+                            "tests/test_oracle_fermions.py", "tests/test_oracle_species.py",
+                            "tests/test_oracle_init.py"],
                            cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
