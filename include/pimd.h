@@ -150,6 +150,20 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
 /* Destroys the host-side context (synchronises its stream first).  NULL is a no-op. */
 pimd_status pimd_destroy(pimd_ctx* ctx);
 
+/* Seeded initial state of every replica on the device: positions iid
+ * N(0, pos_sigma[r]^2) and momenta iid N(0, m'/beta) per coordinate (Maxwell-
+ * Boltzmann at beta for the bead mass m'), thermostat chains at rest.  Every
+ * element is a pure function of (seeds[r], array, element index): element e of
+ * array a (a = 0 positions, a = 1 momenta; [dim][P][N] order) is deviate e mod 2
+ * of the Box-Muller pair k = e/2, drawn with the counter-based generator
+ * Philox4x32-10 (Salmon et al., SC11) at counter {k mod 2^32, k / 2^32, a, 0}
+ * and key {seed mod 2^32, seed / 2^32}: with words w0..w3,
+ * u1 = (w1 2^21 + floor(w0 / 2^11) + 1/2) 2^-53, u2 likewise from w3, w2, and the
+ * deviates are sqrt(-2 ln u1) cos(2 pi u2), sqrt(-2 ln u1) sin(2 pi u2).
+ * pos_sigma and seeds are host arrays of n_replicas entries; pos_sigma[r]
+ * must be finite and >= 0.  Invalidates the forces.  Synchronises. */
+pimd_status pimd_init_system(pimd_ctx* ctx, const double* pos_sigma, const uint64_t* seeds);
+
 /* Sets positions x and (optionally) momenta p of replica r, layout [dim][P][N].
  * nhc (optional) holds the thermostat state as [2][nhc_len][dim][P][N]
  * (positions eta, then velocities v_eta); NULL zeroes it (p NULL zeroes p).
@@ -231,7 +245,7 @@ pimd_status pimd_debug_probs(pimd_ctx* ctx, int32_t r, double* G);
  * independent cross-check and as a cost reference.  If ms is not NULL it
  * receives the summed device time of the kernel launches (HIP events on the
  * context's stream), copies excluded.  PIMD_ERR_STATE before any
- * pimd_set_state.  Synchronises. */
+ * pimd_set_state or pimd_init_system.  Synchronises. */
 pimd_status pimd_cycle_energies(pimd_ctx* ctx, int32_t r, double* E, double* ms);
 
 /* Per-kernel timing with HIP events on the stream each kernel is launched

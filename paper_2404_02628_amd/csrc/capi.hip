@@ -56,10 +56,11 @@ enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LI
            S_SPRINGP, S_PAIRP, S_REDP, S_REC, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_SPRINGW, S_PAIRW, S_INTW, S_DBG,
            S_COUNT };
 
-// Doubles of the debug scratch: two potential arrays, or up to 2^20 entries of a dense N x N
-// table (filled in row chunks).
-long long dbg_doubles(int maxn) {
-  return std::max<long long>(2LL * (maxn + 2), std::min<long long>((long long)maxn * maxn, 1LL << 20));
+// Doubles of the debug scratch: two potential arrays, up to 2^20 entries of a dense N x N table
+// (filled in row chunks), or two parameters per replica for the seeded initial state.
+long long dbg_doubles(int maxn, int R) {
+  return std::max<long long>(std::max<long long>(2LL * (maxn + 2), 2LL * R),
+                             std::min<long long>((long long)maxn * maxn, 1LL << 20));
 }
 
 pimd_status validate(const pimd_config* c) {
@@ -193,7 +194,7 @@ void make_plan(const pimd_config* c, Plan& pl) {
   sz[S_SPRINGW] = sizeof(int4) * d.nspringwg;
   sz[S_PAIRW] = sizeof(int4) * std::max<long long>(d.npairwork, 1);
   sz[S_INTW] = sizeof(int4) * d.nintwg;
-  sz[S_DBG] = 8ull * dbg_doubles(maxn);
+  sz[S_DBG] = 8ull * dbg_doubles(maxn, d.R);
   size_t o = 0;
   for (int s = 0; s < S_COUNT; ++s) {
     pl.off[s] = o;
@@ -688,7 +689,7 @@ pimd_status pimd_debug_probs(pimd_ctx* c, int32_t r, double* G) {
   if (!G) return fail(PIMD_ERR_INVALID, "NULL output");
   if (!c->forces_valid) return fail(PIMD_ERR_STATE, "no force evaluation since the last set_state");
   const long long N = c->pl.reps[r].n;
-  const long long rows = std::max<long long>(1, dbg_doubles(c->pl.d.maxn) / N);
+  const long long rows = std::max<long long>(1, dbg_doubles(c->pl.d.maxn, c->pl.d.R) / N);
   for (long long r0 = 0; r0 < N; r0 += rows) {
     const long long nr = std::min(rows, N - r0);
     HIPCHK(launch_debug_probs(c->pl.d, c->w, r, (int)N, (int)r0, (int)nr, c->w.dbg, c->s));
@@ -698,13 +699,33 @@ pimd_status pimd_debug_probs(pimd_ctx* c, int32_t r, double* G) {
   return PIMD_OK;
 }
 
+pimd_status pimd_init_system(pimd_ctx* c, const double* pos_sigma, const uint64_t* seeds) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  if (!pos_sigma || !seeds) return fail(PIMD_ERR_INVALID, "NULL pos_sigma or seeds");
+  const int R = c->pl.d.R;
+  std::vector<double> prm(2 * (size_t)R);
+  for (int r = 0; r < R; ++r) {
+    if (!(pos_sigma[r] >= 0) || !std::isfinite(pos_sigma[r]))
+      return fail(PIMD_ERR_INVALID, "replica " + std::to_string(r) + ": pos_sigma must be finite and >= 0");
+    prm[2 * r] = pos_sigma[r];
+    std::memcpy(&prm[2 * r + 1], &seeds[r], sizeof(double));
+  }
+  HIPCHK(hipStreamSynchronize(c->s));
+  HIPCHK(hipMemcpyAsync(c->w.dbg, prm.data(), sizeof(double) * prm.size(), hipMemcpyHostToDevice, c->s));
+  HIPCHK(launch_init_state(c->pl.d, c->w, c->w.dbg, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  c->forces_valid = false;
+  c->has_state = true;
+  return PIMD_OK;
+}
+
 pimd_status pimd_cycle_energies(pimd_ctx* c, int32_t r, double* E, double* ms) {
   pimd_status st = check_ctx_r(c, r);
   if (st != PIMD_OK) return st;
   if (!E) return fail(PIMD_ERR_INVALID, "NULL output");
   if (!c->has_state) return fail(PIMD_ERR_STATE, "no state set");
   const long long N = c->pl.reps[r].n;
-  const long long rows = std::max<long long>(1, dbg_doubles(c->pl.d.maxn) / N);
+  const long long rows = std::max<long long>(1, dbg_doubles(c->pl.d.maxn, c->pl.d.R) / N);
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   if (!e0 || !e1) return fail(PIMD_ERR_DEVICE, "hipEventCreate failed");
   auto run = [&]() -> pimd_status {

@@ -31,7 +31,7 @@ EXPORTED = [
     "pimd_set_state", "pimd_get_state", "pimd_compute_forces", "pimd_get_forces", "pimd_step",
     "pimd_energies", "pimd_trace", "pimd_density", "pimd_reset_accumulators", "pimd_debug_potentials",
     "pimd_debug_probs", "pimd_profile", "pimd_kernel_times", "pimd_kernel_name", "pimd_synchronize",
-    "pimd_graph_info", "pimd_cycle_energies",
+    "pimd_graph_info", "pimd_cycle_energies", "pimd_init_system",
 ]
 
 
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
         "pimd_synchronize": (C.c_int, [_vp]),
         "pimd_graph_info": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "pimd_cycle_energies": (C.c_int, [_vp, C.c_int32, _dp, _dp]),
+        "pimd_init_system": (C.c_int, [_vp, _dp, C.POINTER(C.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -209,6 +210,13 @@ def pimd_debug_probs(h, r: int, n: int) -> np.ndarray:
     G = np.zeros((n, n))
     _chk(load().pimd_debug_probs(h, r, G.ctypes.data_as(_dp)), "pimd_debug_probs")
     return G
+
+
+def pimd_init_system(h, pos_sigma, seeds):
+    sig = np.ascontiguousarray(pos_sigma, dtype=np.float64)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    _chk(load().pimd_init_system(h, sig.ctypes.data_as(_dp), sd.ctypes.data_as(C.POINTER(C.c_uint64))),
+         "pimd_init_system")
 
 
 def pimd_cycle_energies(h, r: int, n: int):
@@ -333,6 +341,12 @@ class Context:
 
     def probabilities(self, r: int) -> np.ndarray:
         return pimd_debug_probs(self.h, r, self.systems[r].n)
+
+    def init_system(self, pos_sigma, seeds):
+        """Seeded N(0, sigma_r^2) positions and Maxwell-Boltzmann momenta on the device."""
+        if len(pos_sigma) != len(self.systems) or len(seeds) != len(self.systems):
+            raise ValueError("one pos_sigma and one seed per replica")
+        pimd_init_system(self.h, pos_sigma, seeds)
 
     def cycle_energies(self, r: int):
         return pimd_cycle_energies(self.h, r, self.systems[r].n)
