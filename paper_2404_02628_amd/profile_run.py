@@ -27,6 +27,8 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="large_gauss")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--graphs", action="store_true", help="replay steady steps from a HIP graph")
+    ap.add_argument("--kernel-times", action="store_true",
+                    help="also time the steps with the library's HIP-event profiler and print per-kernel averages")
     args = ap.parse_args(argv)
 
     import torch
@@ -63,6 +65,12 @@ def main(argv=None) -> int:
     print(f"{args.workload} {args.path}{' graphs' if args.graphs else ''} R={len(systems)} {args.steps} steps {dt * 1e3:.2f} ms "
           f"({len(systems) * args.steps / dt:.1f} replica-steps/s, {beads * args.steps / dt:.3e} bead-updates/s)",
           flush=True)
+    if args.kernel_times:
+        ctx.profile(True)
+        ctx.step(args.steps, 0)
+        kt = ctx.kernel_times()
+        ctx.profile(False)
+        print("  " + ", ".join(f"{k} {v[0] / v[1] * 1e3:.1f} us" for k, v in kt.items() if v[1] > 0), flush=True)
     ctx.close()
     return 0
 
