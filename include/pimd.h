@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define PIMD_ABI_VERSION 3
+#define PIMD_ABI_VERSION 4
 
 typedef enum {
     PIMD_OK = 0,
@@ -69,6 +69,12 @@ typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
 #define PIMD_FLAG_PAIR_ORDERED 2  /* use the ordered pair kernel even where the symmetric
                                      per-slice kernel would be chosen (mixed precision with at
                                      least 256 interacting slices); for tuning and testing */
+#define PIMD_FLAG_NO_PERSISTENT 4 /* run pimd_step with one launch per kernel and step even when
+                                     every replica is small enough (N <= 64 and dim*P*N <= 512)
+                                     for the persistent kernel, which otherwise runs whole steps
+                                     of every replica (one workgroup each, state on chip) in one
+                                     launch per 4096 steps; its pair term is FP64 in both
+                                     precision modes; for tuning and testing                 */
 
 /* One independent system (replica).  Units are free; the paper uses
  * hbar = m = omega = k_B = 1 (Sec. IV.A). */

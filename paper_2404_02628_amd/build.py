@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpimd.so")
-SOURCES = ["capi.hip", "k_springs.hip", "k_pair.hip", "k_exchange.hip", "k_integrate.hip", "k_cycle_direct.hip", "k_init.hip"]
+SOURCES = ["capi.hip", "k_springs.hip", "k_pair.hip", "k_exchange.hip", "k_integrate.hip", "k_cycle_direct.hip", "k_init.hip", "k_persistent.hip"]
 ARCH = os.environ.get("PIMD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
          # keep the compiler from forming packed-FP32 instructions on its own

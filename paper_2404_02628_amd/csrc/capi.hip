@@ -36,15 +36,21 @@ pimd_status fail(pimd_status st, const std::string& msg) {
       return fail(PIMD_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
-enum Kind { K_SPRINGS = 0, K_PAIR, K_RECURSION, K_REDUCE, K_INT1, K_INT2, K_INTF, K_EST, K_DENS, K_COUNT };
+enum Kind { K_SPRINGS = 0, K_PAIR, K_RECURSION, K_REDUCE, K_INT1, K_INT2, K_INTF, K_EST, K_DENS, K_PERSIST, K_COUNT };
 const char* kKindNames[K_COUNT] = {"springs", "pair", "recursion", "exchange_forces", "integrate_first",
-                                   "integrate_second", "integrate_fused", "estimators", "density"};
+                                   "integrate_second", "integrate_fused", "estimators", "density",
+                                   "persistent_steps"};
+
+// Steps per launch of the persistent kernel (a call with more steps is split).
+constexpr long long kPersistChunk = 4096;
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
 struct Plan {
   Dims d{};
   int jsplit = 1;
+  bool persistent = false;   // every replica fits one workgroup: steps run in the persistent kernel
+  int persist_maxdof = 0;
   std::vector<RepDev> reps;
   std::vector<int4> springwork, pairwork, intwork;
   size_t off[32]{};
@@ -78,7 +84,8 @@ pimd_status validate(const pimd_config* c) {
   if (c->trace_capacity < 0) return fail(PIMD_ERR_INVALID, "trace_capacity must be >= 0");
   if (c->recursion_workgroups < 0 || c->recursion_workgroups > 4096)
     return fail(PIMD_ERR_INVALID, "recursion_workgroups must be in 0..4096");
-  if ((c->flags & ~(PIMD_FLAG_GRAPH | PIMD_FLAG_PAIR_ORDERED)) != 0) return fail(PIMD_ERR_INVALID, "unknown bits in flags");
+  if ((c->flags & ~(PIMD_FLAG_GRAPH | PIMD_FLAG_PAIR_ORDERED | PIMD_FLAG_NO_PERSISTENT)) != 0)
+    return fail(PIMD_ERR_INVALID, "unknown bits in flags");
   for (int r = 0; r < c->n_replicas; ++r) {
     const pimd_replica& q = c->replicas[r];
     std::string where = "replica " + std::to_string(r) + ": ";
@@ -166,6 +173,13 @@ void make_plan(const pimd_config* c, Plan& pl) {
     for (long long d0 = 0; d0 < R.ndof; d0 += kIntBlock) pl.intwork.push_back(make_int4(r, (int)d0, 0, 0));
   }
   d.G = G; d.NPtot = NP; d.XStot = XS; d.maxn = maxn; d.pair_maxn = pair_maxn;
+  // small replicas: whole steps in one persistent launch (unless the caller asks otherwise)
+  pl.persistent = (c->flags & PIMD_FLAG_NO_PERSISTENT) == 0;
+  pl.persist_maxdof = 0;
+  for (int r = 0; r < d.R; ++r) {
+    pl.persistent = pl.persistent && persistent_fits(d.D, d.P, c->replicas[r].n);
+    pl.persist_maxdof = std::max(pl.persist_maxdof, d.D * d.P * c->replicas[r].n);
+  }
   d.nspringwg = (long long)pl.springwork.size();
   d.npairwork = (long long)pl.pairwork.size();
   d.nreducewg = d.nspringwg;
@@ -560,6 +574,18 @@ pimd_status pimd_step(pimd_ctx* c, int64_t n_steps, int32_t sample_every) {
   if (n_steps < 0 || sample_every < 0) return fail(PIMD_ERR_INVALID, "n_steps and sample_every must be >= 0");
   const Dims& d = c->pl.d;
   pimd_status st;
+  if (c->pl.persistent) {
+    bool need = !c->forces_valid;
+    for (long long done = 0; done < n_steps; done += kPersistChunk) {
+      const long long k = std::min<long long>(kPersistChunk, n_steps - done);
+      RUN(K_PERSIST, c->s, launch_persistent(d, c->w, c->pl.persist_maxdof, c->step, k, sample_every, need, c->s));
+      if (sample_every > 0 && (c->step + k) / sample_every > c->step / sample_every) c->evaluated = true;
+      c->step += k;
+      need = false;
+      c->forces_valid = true;
+    }
+    return PIMD_OK;
+  }
   if (!c->forces_valid && n_steps > 0) {
     if ((st = evaluate(c, false, c->s)) != PIMD_OK) return st;
     RUN(K_INT2, c->s, launch_integrate_second(d, c->w, false, c->s));

@@ -108,6 +108,9 @@ hipError_t launch_density(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_debug_potentials(const Dims& d, const DevPtrs& w, int r, double* X, double* Y, hipStream_t s);
 hipError_t launch_debug_probs(const Dims& d, const DevPtrs& w, int r, int n, int row0, int nrows, double* G,
                               hipStream_t s);
+bool persistent_fits(int D, int P, int n);   // one workgroup can hold the replica's state
+hipError_t launch_persistent(const Dims& d, const DevPtrs& w, int maxdof, long long step0, long long nsteps,
+                             int sample_every, bool need_forces, hipStream_t s);
 hipError_t launch_init_state(const Dims& d, const DevPtrs& w, const double* params, hipStream_t s);
 hipError_t launch_cycle_direct(const Dims& d, const DevPtrs& w, int r, int n, int row0, int nrows, double* out,
                                hipStream_t s);

@@ -25,6 +25,7 @@ PIMD_FP64, PIMD_MIXED = 0, 1
 PIMD_HOST, PIMD_DEVICE = 0, 1
 PIMD_FLAG_GRAPH = 1
 PIMD_FLAG_PAIR_ORDERED = 2
+PIMD_FLAG_NO_PERSISTENT = 4
 
 EXPORTED = [
     "pimd_abi_version", "pimd_last_error", "pimd_workspace_bytes", "pimd_create", "pimd_destroy",
@@ -262,7 +263,7 @@ class Context:
     def __init__(self, systems: Sequence[System], precision: str = "mixed", nhc_len: Optional[int] = None,
                  sy_order: int = 3, density_bins: int = 64, density_rmax: float = 6.0, trace_capacity: int = 0,
                  recursion_workgroups: int = 0, graphs: bool = False, pair_kernel: str = "auto",
-                 device: str = "cuda:0"):
+                 persistent: bool = True, device: str = "cuda:0"):
         import torch  # device memory and streams only
 
         if not systems:
@@ -285,7 +286,8 @@ class Context:
         self.cfg = pimd_config(len(systems), p, dim, PIMD_MIXED if precision == "mixed" else PIMD_FP64, m,
                                sy_order, density_bins, trace_capacity, recursion_workgroups,
                                (PIMD_FLAG_GRAPH if graphs else 0) |
-                               (PIMD_FLAG_PAIR_ORDERED if pair_kernel == "ordered" else 0), density_rmax, reps)
+                               (PIMD_FLAG_PAIR_ORDERED if pair_kernel == "ordered" else 0) |
+                               (0 if persistent else PIMD_FLAG_NO_PERSISTENT), density_rmax, reps)
         self.nbytes = pimd_workspace_bytes(self.cfg)
         self.device = torch.device(device)
         with torch.cuda.device(self.device):

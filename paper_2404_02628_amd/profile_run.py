@@ -27,6 +27,8 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="large_gauss")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--graphs", action="store_true", help="replay steady steps from a HIP graph")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="one launch per kernel and step even for replicas small enough for the persistent kernel")
     ap.add_argument("--kernel-times", action="store_true",
                     help="also time the steps with the library's HIP-event profiler and print per-kernel averages")
     args = ap.parse_args(argv)
@@ -50,7 +52,8 @@ def main(argv=None) -> int:
     else:
         base = WORKLOADS[args.workload]
         systems = [base.with_(seed=base.seed + r) for r in range(args.replicas)]
-    ctx = Context(systems, precision=args.path, recursion_workgroups=args.workgroups, graphs=args.graphs)
+    ctx = Context(systems, precision=args.path, recursion_workgroups=args.workgroups, graphs=args.graphs,
+                  persistent=not args.no_persistent)
     for r, sy in enumerate(systems):
         x, p = initial_state(sy)
         ctx.set_state(r, x, p)

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(lib):
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
     assert set(names) == set(lib.EXPORTED)
-    assert lib.pimd_abi_version() == 3
+    assert lib.pimd_abi_version() == 4
 
 
 def _cfg(lib, **over):
@@ -62,7 +62,7 @@ def test_workspace_size_is_positive_and_monotone(lib):
 @pytest.mark.parametrize("over", [
     {"p": 1}, {"dim": 0}, {"dim": 4}, {"precision": 7}, {"nhc_len": 9}, {"sy_order": 2},
     {"density_bins": 0}, {"density_rmax": 0.0}, {"trace_capacity": -1}, {"n_replicas": 0},
-    {"recursion_workgroups": -1}, {"flags": 4}, {"flags": -1},
+    {"recursion_workgroups": -1}, {"flags": 8}, {"flags": -1},
     {"rep": {"n": 0}}, {"rep": {"xi": -0.1}}, {"rep": {"xi": 1.5}}, {"rep": {"beta": 0.0}},
     {"rep": {"pair_amp": -1.0}}, {"rep": {"pair_amp": 1.0, "pair_width": 0.0}}, {"rep": {"dt": 0.0}},
     {"rep": {"n2": -1}}, {"rep": {"n2": 37}}, {"rep": {"n2": 65}}, {"rep": {"mass": -1.0}},

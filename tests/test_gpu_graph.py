@@ -18,7 +18,8 @@ def _systems(name):
 
 
 def _run(systems, precision, sched, graphs):
-    ctx = Context(systems, precision=precision, recursion_workgroups=sched, graphs=graphs)
+    # the graph belongs to the multi-kernel path (small systems would otherwise run persistent)
+    ctx = Context(systems, precision=precision, recursion_workgroups=sched, graphs=graphs, persistent=False)
     try:
         for r, s in enumerate(systems):
             x0, p0 = initial_state(s)
