@@ -3,7 +3,8 @@
 For a fixed set of replicas the knobs are the recursion schedule (`recursion_workgroups`: 0 lets
 the library choose, 1 forces one workgroup per replica and direction, k > 1 a cooperative chain
 with k-1 helpers), the pair kernel (the symmetric per-slice kernel where the library would pick
-it, or the ordered one) and replay of steady steps from a HIP graph.  `tune` times every
+it, or the ordered one), replay of steady steps from a HIP graph, and, for replicas small enough
+(N <= 64, d P N <= 512), the persistent kernel that runs whole steps on chip.  `tune` times every
 candidate for a few MD steps on the device and returns the fastest; `tune_replicas` picks the
 batch size (replica count) with the highest aggregate replica-steps/s.  Both measure, so they
 need a GPU; `candidates` and `pick` are plain functions that tests exercise without one.
@@ -17,15 +18,25 @@ from typing import Callable, Dict, Iterable, List, Optional, Sequence
 from .workloads import System, initial_state
 
 
+PERSIST_MAX_N = 64
+PERSIST_MAX_DOF = 512
+
+
+def persistent_fits(systems: Sequence[System]) -> bool:
+    """Whether the library runs these replicas in its persistent kernel (unless told not to)."""
+    return all(s.n <= PERSIST_MAX_N and s.dim * s.p * s.n <= PERSIST_MAX_DOF for s in systems)
+
+
 @dataclass(frozen=True)
 class Knobs:
     recursion_workgroups: int = 0
     pair_kernel: str = "auto"
     graphs: bool = False
+    persistent: bool = False
 
     def as_kwargs(self) -> Dict:
         return {"recursion_workgroups": self.recursion_workgroups, "pair_kernel": self.pair_kernel,
-                "graphs": self.graphs}
+                "graphs": self.graphs, "persistent": self.persistent}
 
 
 @dataclass
@@ -44,7 +55,7 @@ def candidates(systems: Sequence[System], precision: str) -> List[Knobs]:
         scheds += sorted({h + 1 for h in (1, 4, 16) if h < nblk - 1})
     pairs = ["auto", "ordered"] if (has_pair and precision == "mixed" and
                                     sum(s.p for s in systems if s.pair_amp > 0) >= 256) else ["auto"]
-    out = []
+    out = [Knobs(persistent=True)] if persistent_fits(systems) else []
     for r in scheds:
         for pk in pairs:
             for g in (False, True):
@@ -55,7 +66,8 @@ def candidates(systems: Sequence[System], precision: str) -> List[Knobs]:
 def pick(timings: Dict[Knobs, float]) -> Knobs:
     """Fastest candidate; ties go to the simpler one (library defaults first)."""
     def simplicity(k: Knobs):
-        return (k.graphs, k.pair_kernel != "auto", k.recursion_workgroups != 0, k.recursion_workgroups)
+        return (not k.persistent, k.graphs, k.pair_kernel != "auto", k.recursion_workgroups != 0,
+                k.recursion_workgroups)
     return min(timings, key=lambda k: (timings[k], simplicity(k)))
 
 
@@ -86,9 +98,10 @@ def tune(systems: Sequence[System], precision: str = "mixed", steps: int = 20, w
 
 def tune_replicas(make_systems: Callable[[int], List[System]], counts: Sequence[int], precision: str = "mixed",
                   steps: int = 20, warmup: int = 5, **ctx_kw) -> Dict[int, float]:
-    """Aggregate replica-steps/s for each replica count (library-default knobs)."""
+    """Aggregate replica-steps/s for each replica count (the library's default choices)."""
     out = {}
     for R in counts:
         systems = make_systems(R)
-        out[R] = R / _time_steps(systems, precision, Knobs(), steps, warmup, **ctx_kw)
+        out[R] = R / _time_steps(systems, precision, Knobs(persistent=persistent_fits(systems)), steps, warmup,
+                                 **ctx_kw)
     return out

@@ -14,6 +14,8 @@ def test_candidates_cover_the_schedules_that_apply():
     assert all(k.recursion_workgroups in (0, 1) for k in many)   # batched: no helpers
     tiny = candidates([WORKLOADS["small_ideal"]], "fp64")
     assert all(k.recursion_workgroups in (0, 1) for k in tiny)   # one row block: nothing to help
+    assert Knobs(persistent=True) in tiny                        # small enough for the persistent kernel
+    assert not any(k.persistent for k in one) and not any(k.persistent for k in many)
     assert len(set(candidates(batched_systems(64, 505), "mixed"))) == len(candidates(batched_systems(64, 505), "mixed"))
 
 
@@ -22,3 +24,5 @@ def test_pick_takes_the_fastest_and_breaks_ties_toward_defaults():
     assert pick(t) == Knobs(1, "ordered", True)
     t = {Knobs(1, "auto", True): 1.0, Knobs(0, "auto", False): 1.0, Knobs(1, "auto", False): 1.0}
     assert pick(t) == Knobs(0, "auto", False)
+    t = {Knobs(persistent=True): 1.0, Knobs(0, "auto", False): 1.0}
+    assert pick(t) == Knobs(persistent=True)                     # the library default for small replicas
