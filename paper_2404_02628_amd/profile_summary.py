@@ -27,13 +27,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # Sources whose change invalidates a kernel's counter record.
 KERNEL_SOURCES = {
-    "k_pair_sym_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h"],
-    "k_pair_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h"],
-    "k_pair_f64": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h"],
+    "k_pair_sym_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h",
+                       "paper_2404_02628_amd/csrc/pimd_internal.h"],
+    "k_pair_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h",
+                   "paper_2404_02628_amd/csrc/pimd_internal.h"],
+    "k_pair_f64": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h",
+                   "paper_2404_02628_amd/csrc/pimd_internal.h"],
     "k_recursion": ["paper_2404_02628_amd/csrc/k_exchange.hip", "paper_2404_02628_amd/csrc/fast_exp.h",
-                    "paper_2404_02628_amd/csrc/device_util.h"],
-    "k_integrate": ["paper_2404_02628_amd/csrc/k_integrate.hip", "paper_2404_02628_amd/csrc/fast_exp.h"],
-    "k_springs": ["paper_2404_02628_amd/csrc/k_springs.hip"],
+                    "paper_2404_02628_amd/csrc/device_util.h", "paper_2404_02628_amd/csrc/pimd_internal.h"],
+    "k_integrate": ["paper_2404_02628_amd/csrc/k_integrate.hip", "paper_2404_02628_amd/csrc/nhc.h",
+                    "paper_2404_02628_amd/csrc/fast_exp.h", "paper_2404_02628_amd/csrc/pimd_internal.h"],
+    "k_springs": ["paper_2404_02628_amd/csrc/k_springs.hip", "paper_2404_02628_amd/csrc/pimd_internal.h"],
 }
 
 
