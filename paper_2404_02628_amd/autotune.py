@@ -52,7 +52,7 @@ def candidates(systems: Sequence[System], precision: str) -> List[Knobs]:
     scheds = [0, 1]
     if len(systems) <= 8 and nblk > 2:
         # a few cooperative helper counts between "one helper" and "as many as fit"
-        scheds += sorted({h + 1 for h in (1, 4, 16) if h < nblk - 1})
+        scheds += sorted({h + 1 for h in (1, 4, 16, 32, 64, 128) if h < nblk - 1})
     pairs = ["auto", "ordered"] if (has_pair and precision == "mixed" and
                                     sum(s.p for s in systems if s.pair_amp > 0) >= 256) else ["auto"]
     out = [Knobs(persistent=True)] if persistent_fits(systems) else []
