@@ -9,7 +9,10 @@
 // high part (k * hi is exact for |k| < 2^21) and a low correction:
 //   64/ln2 = 92.33248261689366, hi = 0x1.62e42fee00000p-7, lo = 0x1.a39ef35793c76p-39.
 // About 14 vector instructions instead of ~26 for the library exp; results are within a few
-// ulp, far below the 1e-10 parity bar.
+// ulp, far below the 1e-10 parity bar.  The function has no branches: the argument is clamped
+// to the finite range and the special cases (underflow to 0, overflow to inf, NaN) are selected
+// at the end, so the compiler can interleave independent calls instead of running each one's
+// exec-masked regions in turn.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -24,21 +27,22 @@ __host__ __device__ inline double fast_exp(double x, const double* tab) {
   const double kInvL = 92.33248261689366;          // 64 / ln 2
   const double kL1 = 0x1.62e42fee00000p-7;         // high 32 bits of ln2 / 64
   const double kL2 = 0x1.a39ef35793c76p-39;        // ln2 / 64 - kL1
-  if (!(x > -745.2)) return x != x ? x : 0.0;     // underflow (and -inf) to 0, NaN through
-  if (x > 709.8) return __builtin_huge_val();
-  const double kd = rint(x * kInvL);
+  const double xc = fmin(fmax(x, -745.2), 709.8);  // NaN -> -745.2 (fmax drops it); selected below
+  const double kd = rint(xc * kInvL);
   const int k = (int)kd;
-  double r = fma(-kd, kL1, x);
+  double r = fma(-kd, kL1, xc);
   r = fma(-kd, kL2, r);
   const int j = k & 63;
-  const int m = (k - j) / 64;
+  const int m = (k - j) >> 6;                      // k - j is a multiple of 64
   // e^r - 1 = r + r^2/2 + r^3/6 + r^4/24 + r^5/120
   double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
   q = fma(q, r, 1.0 / 6.0);
   q = fma(q, r, 0.5);
   q = q * r * r + r;
   const double t = tab[j];
-  return ldexp(fma(t, q, t), m);
+  const double v = ldexp(fma(t, q, t), m);
+  // x <= -745.2 (and -inf) underflows to 0, x > 709.8 overflows, NaN passes through
+  return x > -745.2 ? (x > 709.8 ? __builtin_huge_val() : v) : (x != x ? x : 0.0);
 }
 
 }  // namespace pimd

@@ -27,5 +27,7 @@ int main() {
   printf("special %g %g %g %g %d\n", pimd::fast_exp(0.0, tab), pimd::fast_exp(-INFINITY, tab),
          pimd::fast_exp(-800.0, tab), pimd::fast_exp(-744.0, tab) / std::exp(-744.0),
          (int)std::isnan(pimd::fast_exp(NAN, tab)));
+  printf("overflow %d %d %d\n", (int)std::isinf(pimd::fast_exp(1000.0, tab)),
+         (int)std::isinf(pimd::fast_exp(INFINITY, tab)), (int)std::isfinite(pimd::fast_exp(709.0, tab)));
   return 0;
 }

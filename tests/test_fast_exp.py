@@ -21,3 +21,4 @@ def test_fast_exp_accuracy():
     one, zero_inf, zero_under, ratio_sub, isnan = out[1].split()[1:]
     assert float(one) == 1.0 and float(zero_inf) == 0.0 and float(zero_under) == 0.0
     assert abs(float(ratio_sub) - 1.0) < 1e-6 and isnan == "1"
+    assert out[2].split()[1:] == ["1", "1", "1"], out[2]
