@@ -262,18 +262,24 @@ template <int D, class SH>
 __device__ inline void inblock_alpha(SH& sh, int cur, int blk, int i, const double (&pi)[D], double rho,
                                      bool valid, double bc, double lnxi, int bnd) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // every record is read before the first store: the compiler cannot tell that the stores to Am
+  // miss the records, and would otherwise wait out each load's latency in turn
+  double4 r4[SH::kCols];
+#pragma unroll
+  for (int u = 0; u < SH::kCols; ++u) r4[u] = sh.col[cur][wave * SH::kCols + u];
+  double v[SH::kCols];
 #pragma unroll
   for (int u = 0; u < SH::kCols; ++u) {
-    const int sc = wave * SH::kCols + u;
-    const int j = blk * kTile + sc;
-    const double4 r4 = sh.col[cur][sc];
-    const double qv[3] = {r4.x, r4.y, r4.z};
+    const int j = blk * kTile + wave * SH::kCols + u;
+    const double qv[3] = {r4[u].x, r4[u].y, r4[u].z};
     double d2 = 0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c) { const double t = pi[c] - qv[c]; d2 = fma(t, t, d2); }
-    const double v = xi_pow_log(i - 1 - j, lnxi) + rho + r4.w - bc * d2;
-    sh.Am[sc * kTile + lane] = (valid && j < i && (i <= bnd || j >= bnd)) ? v : -INFINITY;
+    const double a = xi_pow_log(i - 1 - j, lnxi) + rho + r4[u].w - bc * d2;
+    v[u] = (valid && j < i && (i <= bnd || j >= bnd)) ? a : -INFINITY;
   }
+#pragma unroll
+  for (int u = 0; u < SH::kCols; ++u) sh.Am[(wave * SH::kCols + u) * kTile + lane] = v[u];
 }
 
 
@@ -336,22 +342,32 @@ __device__ inline double substitute_regs(const double* __restrict__ Am, double a
 template <int D, class SH>
 __device__ inline void scaled_coefficients(SH& sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int K = kTile / 2 / SH::kWaves;
+  // all loads first, then the exponentials (independent, so they interleave), then all stores
+  double arg[K];
+  int idx[K];
+  bool act[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int s = wave * K + k;                          // 0..31
+    const bool lower = lane > s;
+    const int col = lower ? s : kTile - 1 - s;
+    const int row = lower ? lane : kTile - s + lane;     // lanes 0..s-1 -> rows 64-s..63
+    act[k] = lower || lane < s;
+    idx[k] = act[k] ? col * kTile + row : 0;
+    arg[k] = act[k] ? sh.Am[idx[k]] + sh.Dl[col] - sh.Dl[row] : 0.0;
+  }
+  double e[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) e[k] = fast_exp(arg[k], sh.tab);
 #pragma unroll
   for (int u = 0; u < SH::kCols; ++u) {
     const int sc = wave * SH::kCols + u;
     if (lane <= sc) sh.Am[sc * kTile + lane] = 0.0;
   }
 #pragma unroll
-  for (int k = 0; k < kTile / 2 / SH::kWaves; ++k) {
-    const int s = wave * (kTile / 2 / SH::kWaves) + k;   // 0..31
-    const bool lower = lane > s;
-    const int col = lower ? s : kTile - 1 - s;
-    const int row = lower ? lane : kTile - s + lane;     // lanes 0..s-1 -> rows 64-s..63
-    if (lower || lane < s) {
-      const int idx = col * kTile + row;
-      sh.Am[idx] = fast_exp(sh.Am[idx] + sh.Dl[col] - sh.Dl[row], sh.tab);
-    }
-  }
+  for (int k = 0; k < K; ++k)
+    if (act[k]) sh.Am[idx[k]] = e[k];
 }
 
 // G_i, the completed column record of row i (LDS and global), the next block's column records,
