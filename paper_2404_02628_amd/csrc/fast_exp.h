@@ -45,4 +45,39 @@ __host__ __device__ inline double fast_exp(double x, const double* tab) {
   return x > -745.2 ? (x > 709.8 ? __builtin_huge_val() : v) : (x != x ? x : 0.0);
 }
 
+// Natural logarithm for the FP64 kernels, branch-free and without tables.  Write
+// x = 2^e m with m in [sqrt(1/2), sqrt(2)); with u = (m - 1)/(m + 1), |u| <= 0.1716,
+//   log m = 2 atanh u = 2u (1 + u^2/3 + u^4/5 + ... + u^18/19) + O(u^21/21)
+// (the neglected terms are below 3e-17 of the result), and log x = e ln2 + log m with ln2 split
+// into a 42-bit high part (e * hi is exact for |e| < 2^11) and a low correction:
+//   hi = 0x1.62e42fefa3800p-1, lo = 0x1.ef35793c76730p-45.
+// About 35 vector instructions instead of ~110 for the library log (which carries double-double
+// intermediate precision); results are within a few ulp.  0 gives -inf, +inf gives +inf, and
+// negative arguments and NaN give NaN.
+__host__ __device__ inline double fast_log(double x) {
+  const double kL2hi = 0x1.62e42fefa3800p-1;
+  const double kL2lo = 0x1.ef35793c76730p-45;
+  int e;
+  double m = frexp(x, &e);                          // x = m 2^e, m in [1/2, 1)
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? 2.0 * m : m;
+  e = lo ? e - 1 : e;
+  const double u = (m - 1.0) / (m + 1.0);
+  const double z = u * u;
+  double q = fma(z, 1.0 / 19.0, 1.0 / 17.0);
+  q = fma(q, z, 1.0 / 15.0);
+  q = fma(q, z, 1.0 / 13.0);
+  q = fma(q, z, 1.0 / 11.0);
+  q = fma(q, z, 1.0 / 9.0);
+  q = fma(q, z, 1.0 / 7.0);
+  q = fma(q, z, 1.0 / 5.0);
+  q = fma(q, z, 1.0 / 3.0);
+  const double u2 = 2.0 * u;
+  const double lm = fma(u2 * z, q, u2);             // 2u + 2u z q
+  const double de = (double)e;
+  const double v = fma(de, kL2hi, fma(de, kL2lo, lm));
+  const double inf = __builtin_huge_val();
+  return (x > 0.0 && x < inf) ? v : (x == 0.0 ? -inf : (x == inf ? inf : __builtin_nan("")));
+}
+
 }  // namespace pimd

@@ -71,7 +71,7 @@ struct RecMap {
     }
   }
   __device__ inline double row_rho(int i, double lv) const {
-    return dir == 0 ? beta * lv - log((double)(i > bnd ? i - bnd : i)) : beta * lv;
+    return dir == 0 ? beta * lv - fast_log((double)(i > bnd ? i - bnd : i)) : beta * lv;
   }
   // column point q_j, for 0 <= j <= N-1
   __device__ inline void col_load(int j, double (&q)[D]) const {
@@ -84,7 +84,7 @@ struct RecMap {
     }
   }
   __device__ inline double col_gamma(int j) const {
-    return dir == 0 ? 0.0 : -log((double)(j < bnd ? bnd - j : N - j));
+    return dir == 0 ? 0.0 : -fast_log((double)(j < bnd ? bnd - j : N - j));
   }
 };
 
@@ -380,7 +380,7 @@ __device__ inline void finish_rows(SH& sh, int blk, int cur, int N, bool valid, 
   const int i = blk * kTile + lane;
   sh.Wl[lane] = wi;
   if (i <= N) {
-    const double Gi = Di + log(wi);
+    const double Gi = Di + fast_log(wi);
     G[i] = Gi;
     if (i < N) {
       double4 r4 = sh.col[cur][lane];
@@ -429,7 +429,7 @@ __device__ inline void solve_block(SH& sh, int blk, int cur, int N, bool valid, 
 #pragma unroll
       for (int q = 0; q <= D; ++q) PS[q] = fma(sh.pp[w][q][lane], f, PS[q]);
     }
-    LB = (S > 0.0) ? M + log(S) : -INFINITY;
+    LB = (S > 0.0) ? M + fast_log(S) : -INFINITY;
     const double invS = S > 0.0 ? 1.0 / S : 0.0;
 #pragma unroll
     for (int q = 0; q <= D; ++q) cy.pb[q] = PS[q] * invS;
