@@ -20,6 +20,8 @@
 
 namespace pimd {
 
+constexpr int kBeadChunk = 8;   // beads loaded together per particle
+
 template <int D, bool SHADOW>
 __global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restrict__ reps,
                                                           const int4* __restrict__ work,
@@ -62,15 +64,26 @@ __global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restri
       double d = rp - r0;
       e_int += d * d;
       double rc = rp;
-      for (int j = 1; j < P - 1; ++j) {
-        double rn = xa[(long long)(j + 1) * N + l];
-        fa[(long long)j * N + l] = -kap * (2.0 * rc - rn - rm) - trap * rc;
-        ut += rc * rc;
-        if (SHADOW) xsr[((long long)j * R.npad + l) * dp + a] = (float)rc * kscale;
-        double dd = rn - rc;
-        e_int += dd * dd;
-        rm = rc;
-        rc = rn;
+      // beads in chunks: the chunk's loads are issued together, so each chunk waits out one
+      // memory latency instead of one per bead (the sums keep their bead order)
+      for (int j0 = 1; j0 < P - 1; j0 += kBeadChunk) {
+        double nx[kBeadChunk];
+#pragma unroll
+        for (int u = 0; u < kBeadChunk; ++u) nx[u] = xa[(long long)min(j0 + u + 1, P - 1) * N + l];
+#pragma unroll
+        for (int u = 0; u < kBeadChunk; ++u) {
+          const int j = j0 + u;
+          if (j < P - 1) {
+            const double rn = nx[u];
+            fa[(long long)j * N + l] = -kap * (2.0 * rc - rn - rm) - trap * rc;
+            ut += rc * rc;
+            if (SHADOW) xsr[((long long)j * R.npad + l) * dp + a] = (float)rc * kscale;
+            const double dd = rn - rc;
+            e_int += dd * dd;
+            rm = rc;
+            rc = rn;
+          }
+        }
       }
       // rc is bead P
       fa[(long long)(P - 1) * N + l] = -trap * rc;
