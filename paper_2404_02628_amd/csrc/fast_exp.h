@@ -9,10 +9,10 @@
 // high part (k * hi is exact for |k| < 2^21) and a low correction:
 //   64/ln2 = 92.33248261689366, hi = 0x1.62e42fee00000p-7, lo = 0x1.a39ef35793c76p-39.
 // About 14 vector instructions instead of ~26 for the library exp; results are within a few
-// ulp, far below the 1e-10 parity bar.  The function has no branches: the argument is clamped
-// to the finite range and the special cases (underflow to 0, overflow to inf, NaN) are selected
-// at the end, so the compiler can interleave independent calls instead of running each one's
-// exec-masked regions in turn.
+// ulp, far below the 1e-10 parity bar.  The function has no branches, so the compiler can
+// interleave independent calls instead of running each one's exec-masked regions in turn: the
+// argument is clamped to [-800, 709.8], where ldexp itself produces the limits (exactly 0 below
+// about -745.2, inf above ln(DBL_MAX) = 709.78), and only NaN is selected at the end.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -27,7 +27,7 @@ __host__ __device__ inline double fast_exp(double x, const double* tab) {
   const double kInvL = 92.33248261689366;          // 64 / ln 2
   const double kL1 = 0x1.62e42fee00000p-7;         // high 32 bits of ln2 / 64
   const double kL2 = 0x1.a39ef35793c76p-39;        // ln2 / 64 - kL1
-  const double xc = fmin(fmax(x, -745.2), 709.8);  // NaN -> -745.2 (fmax drops it); selected below
+  const double xc = fmin(fmax(x, -800.0), 709.8);  // -inf -> -800 -> 0; NaN -> -800, selected below
   const double kd = rint(xc * kInvL);
   const int k = (int)kd;
   double r = fma(-kd, kL1, xc);
@@ -41,8 +41,7 @@ __host__ __device__ inline double fast_exp(double x, const double* tab) {
   q = q * r * r + r;
   const double t = tab[j];
   const double v = ldexp(fma(t, q, t), m);
-  // x <= -745.2 (and -inf) underflows to 0, x > 709.8 overflows, NaN passes through
-  return x > -745.2 ? (x > 709.8 ? __builtin_huge_val() : v) : (x != x ? x : 0.0);
+  return x != x ? x : v;
 }
 
 // Natural logarithm for the FP64 kernels, branch-free and without tables.  Write

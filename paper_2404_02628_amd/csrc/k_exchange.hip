@@ -137,15 +137,17 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
 #pragma unroll
     for (int u = 0; u < 4; ++u) dst[u] = rec[min(j0 + u, jb - 1)];
   };
+  // groups of four columns; only the last group can be partial, and only it masks its terms
   if (ja < jb) ld(cur, ja);
   for (int j0 = ja; j0 < jb; j0 += 4) {
     if (j0 + 4 < jb) ld(nxt, j0 + 4);
+    const bool full = j0 + 4 <= jb;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = j0 + u;
       double d2;
       double t = term_of<D, XM>(rc, pi, cur[u], j, d2);
-      if (j >= jb) t = -INFINITY;
+      if (!full && j >= jb) t = -INFINITY;
       const double e = fast_exp(t - R, tab);
       const int h = u & 1;
       s[h] += e;
