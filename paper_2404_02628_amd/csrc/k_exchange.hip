@@ -137,6 +137,8 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
 #pragma unroll
     for (int u = 0; u < 4; ++u) dst[u] = rec[min(j0 + u, jb - 1)];
   };
+  // the reference enters the row constant once instead of every term
+  const RowCtx rr{rc.i, rc.rowc - R, rc.bc, rc.lnxi};
   // groups of four columns; only the last group can be partial, and only it masks its terms
   if (ja < jb) ld(cur, ja);
   for (int j0 = ja; j0 < jb; j0 += 4) {
@@ -146,9 +148,9 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
     for (int u = 0; u < 4; ++u) {
       const int j = j0 + u;
       double d2;
-      double t = term_of<D, XM>(rc, pi, cur[u], j, d2);
+      double t = term_of<D, XM>(rr, pi, cur[u], j, d2);   // t_{i,j} - R
       if (!full && j >= jb) t = -INFINITY;
-      const double e = fast_exp(t - R, tab);
+      const double e = fast_exp(t, tab);
       const int h = u & 1;
       s[h] += e;
       const double qv[3] = {cur[u].x, cur[u].y, cur[u].z};

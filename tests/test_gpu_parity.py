@@ -249,7 +249,8 @@ def test_nonfinite_state_is_reported(orc):
 
 def test_schedules_agree_and_repeat(orc):
     """The cooperative schedule (chain + helpers) and the one-workgroup schedule give the same
-    forces and potentials to rounding, and repeated evaluations (new epochs) repeat exactly."""
+    forces and potentials to rounding (c_X and eps max|X|, as in the parity bars), and repeated
+    evaluations (new epochs) repeat exactly."""
     from paper_2404_02628_amd.pimd import Context
     from paper_2404_02628_amd.workloads import thermal_rings
     s = System(n=700, p=8, dim=3, beta=2.0, xi=0.6, pair_amp=1.0, pair_width=0.5, sigma=2.0, seed=31)
@@ -268,7 +269,12 @@ def test_schedules_agree_and_repeat(orc):
             out[sched] = (f1, X1, Y1)
         finally:
             ctx.close()
+    # the schedules sum in different orders and round the exponents (of magnitude |X|)
+    # differently, so they agree to eps max|X| in the potentials and to c_X in the forces
+    X = out[1][1]
+    eps_x = np.finfo(float).eps * float(np.max(np.abs(X)))
+    c_x = 32 * eps_x
     for sched in (3, 12):
-        assert rel_max(out[sched][0], out[1][0]) <= 1e-12
-        assert rel_max(out[sched][1], out[1][1]) <= 1e-13
-        assert rel_max(out[sched][2][1:], out[1][2][1:]) <= 1e-13
+        assert force_err(out[sched][0], out[1][0], s, x) <= c_x, (sched, force_err(out[sched][0], out[1][0], s, x), c_x)
+        assert float(np.max(np.abs(out[sched][1] - X))) <= 8 * eps_x
+        assert float(np.max(np.abs(out[sched][2][1:] - out[1][2][1:]))) <= 8 * eps_x
