@@ -14,18 +14,6 @@
 
 namespace pimd {
 
-template <int M>
-__device__ inline void nhc_half(double& p, const RepDev& R, double* eta, double* veta, long long gi, long long G,
-                                const SyW& sy, const double* tab) {
-  if (M == 0) return;
-  double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
-#pragma unroll
-  for (int k = 0; k < M; ++k) { e[k] = eta[k * G + gi]; v[k] = veta[k * G + gi]; }
-  nhc_propagate(p, R.inv_mp, e, v, M, R.inv_q, R.kT, 0.5 * R.dt, sy, tab);
-#pragma unroll
-  for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
-}
-
 // Thread -> degree of freedom.  Work item {rep, first dof} covers kIntBlock consecutive dofs of
 // one replica; dofs are elementwise-independent, so the launch is a flat coalesced stream.
 // mode 0: first half  (NHC(dt/2), p += F dt/2, x += p dt/m')
@@ -39,49 +27,59 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
                                                          const double* __restrict__ fpair, double* __restrict__ eta,
                                                          double* __restrict__ veta, long long G, SyW sy) {
   __shared__ double tab[kExpTable];
-  if (M > 0 && MODE != 2) {
-    if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
-    __syncthreads();
-  }
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
   const long long li = (long long)wk.y + threadIdx.x;
-  if (li >= R.ndof) return;
-  const long long gi = R.dof + li;
+  const bool ok = li < R.ndof;
+  const long long gi = R.dof + (ok ? li : 0);
   const double hdt = 0.5 * R.dt;
-  if (MODE == 0) {
-    double pv = p[gi];
-    nhc_half<M>(pv, R, eta, veta, gi, G, sy, tab);
-    pv += hdt * f[gi];
-    x[gi] += R.dt_mp * pv;
-    p[gi] = pv;
-    return;
-  }
+  // Every operand is loaded up front (before the table barrier), so a thread waits out one
+  // memory latency rather than one per dependence.  The pair forces are read even without a
+  // pair term (the buffer is part of the workspace either way) and selected away.
+  constexpr bool kX = MODE == 0 || MODE == 3;
+  constexpr bool kP = MODE != 2;
+  constexpr bool kPair = MODE != 0;
+  constexpr bool kChain = M > 0 && MODE != 2;
   double fv = f[gi];
-  if (R.amp > 0.0) fv += fpair[gi];
-  // the total force is kept for readers of the last evaluation; in the fused pass the next
-  // evaluation overwrites it unread
-  if (MODE != 3) f[gi] = fv;
-  if (MODE == 2) return;
-  double pv = p[gi] + hdt * fv;
-  if (MODE == 1) {
-    nhc_half<M>(pv, R, eta, veta, gi, G, sy, tab);
-    p[gi] = pv;
-    return;
-  }
-  // MODE 3: both thermostat half-steps on the chain held in registers
-  if (M > 0) {
-    double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
+  const double fpv = kPair ? fpair[gi] : 0.0;
+  double pv = kP ? p[gi] : 0.0;
+  const double xv = kX ? x[gi] : 0.0;
+  double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
 #pragma unroll
-    for (int k = 0; k < M; ++k) { e[k] = eta[k * G + gi]; v[k] = veta[k * G + gi]; }
-    nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
-    nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
+  for (int k = 0; k < (M > 0 ? M : 1); ++k) {
+    e[k] = kChain ? eta[k * G + gi] : 0.0;
+    v[k] = kChain ? veta[k * G + gi] : 0.0;
+  }
+  if (kChain) {
+    if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
+    __syncthreads();
+  }
+  if (!ok) return;
+  if (kPair) fv = R.amp > 0.0 ? fv + fpv : fv;
+  if (MODE == 0) {
+    if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    pv += hdt * fv;
+    x[gi] = xv + R.dt_mp * pv;
+    p[gi] = pv;
+  } else {
+    // the total force is kept for readers of the last evaluation; in the fused pass the next
+    // evaluation overwrites it unread
+    if (MODE != 3) f[gi] = fv;
+    if (MODE == 2) return;
+    pv += hdt * fv;
+    if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    if (MODE == 3) {
+      // second thermostat half-step of this step and first of the next, chain in registers
+      if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
+      pv += hdt * fv;
+      x[gi] = xv + R.dt_mp * pv;
+    }
+    p[gi] = pv;
+  }
+  if (kChain) {
 #pragma unroll
     for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
   }
-  pv += hdt * fv;
-  x[gi] += R.dt_mp * pv;
-  p[gi] = pv;
 }
 
 // One workgroup per replica: kinetic and thermostat energies over all dofs plus the
