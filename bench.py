@@ -199,7 +199,9 @@ def main():
 
     from paper_2404_02628_amd import autotune
 
-    # plain FP64 path: one replica, with its own best launch choices
+    # plain FP64 path: one replica, with its own best launch choices.  Graph replay is not among
+    # the candidates: once a process has replayed a captured graph, the runtime slows every later
+    # kernel dispatch of the process, which would distort all measurements below.
     tune64 = autotune.tune(bench_systems(1), "fp64", steps=20, warmup=5)
     t64, _, _ = run_path("fp64", 1, args.steps, args.warmup, knobs=tune64.best)
     fp64_sps = args.steps / t64

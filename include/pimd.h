@@ -65,7 +65,10 @@ typedef enum {
 typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
 
 /* pimd_config.flags */
-#define PIMD_FLAG_GRAPH 1      /* replay steady MD steps from a captured HIP graph (default: direct launches) */
+#define PIMD_FLAG_GRAPH 1      /* replay steady MD steps from a captured HIP graph (default: direct launches).
+                                  Note: on ROCm 7, once a process has captured and replayed a graph,
+                                  every later kernel dispatch of the process costs ~35 us more
+                                  (measured on MI355X), contexts without this flag included. */
 #define PIMD_FLAG_PAIR_ORDERED 2  /* use the ordered pair kernel even where the symmetric
                                      per-slice kernel would be chosen (mixed precision with at
                                      least 256 interacting slices); for tuning and testing */

@@ -45,8 +45,11 @@ class TuneResult:
     seconds_per_step: Dict[Knobs, float] = field(default_factory=dict)
 
 
-def candidates(systems: Sequence[System], precision: str) -> List[Knobs]:
-    """The candidate set for these replicas: schedules that differ in practice only."""
+def candidates(systems: Sequence[System], precision: str, graphs: bool = False) -> List[Knobs]:
+    """The candidate set for these replicas: schedules that differ in practice only.  Graph replay
+    is a candidate only on request: once a process has captured and replayed a step graph, the
+    ROCm runtime adds ~35 us to every later kernel dispatch of that process (measured on MI355X:
+    a 15 us spring kernel then takes 46 us), so timing it would slow everything timed after it."""
     has_pair = any(s.pair_amp > 0 for s in systems)
     nblk = max((s.n + 64) // 64 for s in systems)
     scheds = [0, 1]
@@ -58,7 +61,7 @@ def candidates(systems: Sequence[System], precision: str) -> List[Knobs]:
     out = [Knobs(persistent=True)] if persistent_fits(systems) else []
     for r in scheds:
         for pk in pairs:
-            for g in (False, True):
+            for g in ((False, True) if graphs else (False,)):
                 out.append(Knobs(r, pk, g))
     return out
 

@@ -6,7 +6,8 @@ from paper_2404_02628_amd.workloads import WORKLOADS, batched_systems
 def test_candidates_cover_the_schedules_that_apply():
     big = WORKLOADS["large_gauss"]
     one = candidates([big], "fp64")
-    assert Knobs(0, "auto", False) in one and Knobs(1, "auto", True) in one
+    assert Knobs(0, "auto", False) in one and not any(k.graphs for k in one)   # graphs only on request
+    assert Knobs(1, "auto", True) in candidates([big], "fp64", graphs=True)
     assert any(k.recursion_workgroups > 1 for k in one)          # cooperative helper counts
     assert all(k.pair_kernel == "auto" for k in one)             # FP64: ordered kernel only
     many = candidates([big.with_(seed=k) for k in range(16)], "mixed")
