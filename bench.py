@@ -144,8 +144,8 @@ def traffic_bytes(kind, precision, R):
     return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
 
-def cpu_baseline(sample_steps=12):
-    """The CPU oracle as it stands (sequential FP64, one thread) on a bounded sample."""
+def cpu_baseline(sample_steps=40):
+    """The CPU oracle as it stands (sequential FP64, one thread) on a bounded sample (about 15 s)."""
     import oracle
     s = WORKLOADS["large_gauss"]
     par = oracle.OracleParams(n=s.n, p=s.p, dim=s.dim, beta=s.beta, xi=s.xi, pair_amp=s.pair_amp,
