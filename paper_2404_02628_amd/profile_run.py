@@ -27,6 +27,7 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="large_gauss")
     ap.add_argument("--copy-mib", type=int, default=512)
     ap.add_argument("--graphs", action="store_true", help="replay steady steps from a HIP graph")
+    ap.add_argument("--n2", type=int, default=0, help="particles of a second species in every replica")
     ap.add_argument("--no-persistent", action="store_true",
                     help="one launch per kernel and step even for replicas small enough for the persistent kernel")
     ap.add_argument("--kernel-times", action="store_true",
@@ -51,7 +52,7 @@ def main(argv=None) -> int:
         systems = batched_systems(64, 505)
     else:
         base = WORKLOADS[args.workload]
-        systems = [base.with_(seed=base.seed + r) for r in range(args.replicas)]
+        systems = [base.with_(seed=base.seed + r, n2=args.n2) for r in range(args.replicas)]
     ctx = Context(systems, precision=args.path, recursion_workgroups=args.workgroups, graphs=args.graphs,
                   persistent=not args.no_persistent)
     for r, sy in enumerate(systems):

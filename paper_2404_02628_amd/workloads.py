@@ -57,6 +57,8 @@ WORKLOADS = {
                           seed=303),
     "huge_ideal_10k": System(n=10000, p=16, dim=3, beta=2.0, xi=1.0, pair_amp=0.0, sigma=3.0, seed=404),
     "huge_ideal_40k": System(n=40000, p=16, dim=3, beta=2.0, xi=1.0, pair_amp=0.0, sigma=3.0, seed=405),
+    # one replica of the xi-extrapolation ensembles (N = 3 ideal particles, d = 2, beta = 1, P = 12)
+    "xi_ensemble_n3": System(n=3, p=12, dim=2, beta=1.0, xi=1.0, pair_amp=0.0, sigma=1.0, seed=0),
 }
 
 
