@@ -132,7 +132,6 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int q = 0; q <= D; ++q) pq[h][q] = 0.0;
-  double4 cur[4], nxt[4];
   auto ld = [&](double4 (&dst)[4], int j0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) dst[u] = rec[min(j0 + u, jb - 1)];
@@ -140,26 +139,32 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
   // the reference enters the row constant once instead of every term
   const RowCtx rr{rc.i, rc.rowc - R, rc.bc, rc.lnxi};
   // groups of four columns; only the last group can be partial, and only it masks its terms
-  if (ja < jb) ld(cur, ja);
-  for (int j0 = ja; j0 < jb; j0 += 4) {
-    if (j0 + 4 < jb) ld(nxt, j0 + 4);
+  auto group = [&](const double4 (&g)[4], int j0) {
     const bool full = j0 + 4 <= jb;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = j0 + u;
       double d2;
-      double t = term_of<D, XM>(rr, pi, cur[u], j, d2);   // t_{i,j} - R
+      double t = term_of<D, XM>(rr, pi, g[u], j, d2);   // t_{i,j} - R
       if (!full && j >= jb) t = -INFINITY;
       const double e = fast_exp(t, tab);
       const int h = u & 1;
       s[h] += e;
-      const double qv[3] = {cur[u].x, cur[u].y, cur[u].z};
+      const double qv[3] = {g[u].x, g[u].y, g[u].z};
 #pragma unroll
       for (int c = 0; c < D; ++c) pq[h][c] = fma(e, qv[c], pq[h][c]);
       pq[h][D] = fma(e, d2, pq[h][D]);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+  };
+  // two record buffers in turn, each loaded one group ahead (no register copies between groups)
+  double4 bufA[4], bufB[4];
+  if (ja < jb) ld(bufA, ja);
+  for (int j0 = ja; j0 < jb; j0 += 8) {
+    if (j0 + 4 < jb) ld(bufB, j0 + 4);
+    group(bufA, j0);
+    if (j0 + 4 >= jb) break;
+    if (j0 + 8 < jb) ld(bufA, j0 + 8);
+    group(bufB, j0 + 4);
   }
   s_out = s[0] + s[1];
 #pragma unroll
