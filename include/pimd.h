@@ -201,7 +201,11 @@ pimd_status pimd_get_forces(pimd_ctx* ctx, int32_t r, double* f, pimd_mem where)
  * density histogram and the trace are taken every `sample_every` steps
  * (0 = never).  The first call evaluates the forces of the initial state.
  * Enqueued only.  Errors: PIMD_ERR_INVALID (n_steps < 0, sample_every < 0).
- * Steps that are neither sampled nor the first or last of the call are all the
+ * When every replica has N <= 64 and dim*P*N <= 512 (and PIMD_FLAG_NO_PERSISTENT
+ * is not set) the steps run in the persistent kernel: one launch per 4096 steps,
+ * one workgroup per replica with its state on chip, FP64 pair term in both
+ * precision modes; PIMD_FLAG_GRAPH has no effect then.  Otherwise:
+ * steps that are neither sampled nor the first or last of the call are all the
  * same launch sequence (evaluation plus the fused second/first integrator
  * halves); with PIMD_FLAG_GRAPH (and profiling off) that sequence is captured
  * once into a HIP graph and replayed on the stream.  If the device cannot
@@ -210,7 +214,8 @@ pimd_status pimd_get_forces(pimd_ctx* ctx, int32_t r, double* f, pimd_mem where)
  * other instead of on two streams, so it pays only for small systems. */
 pimd_status pimd_step(pimd_ctx* ctx, int64_t n_steps, int32_t sample_every);
 
-/* State of the step graph: *state = 0 not built yet, 1 built and replayed,
+/* State of the step graph: *state = 0 not built yet (and stays 0 while the
+ * steps run in the persistent kernel), 1 built and replayed,
  * 2 not requested (no PIMD_FLAG_GRAPH), 3 capture failed (direct launches);
  * *replays = steps run by graph replay so far.  Either pointer may be NULL. */
 pimd_status pimd_graph_info(pimd_ctx* ctx, int32_t* state, int64_t* replays);
