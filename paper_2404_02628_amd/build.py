@@ -12,6 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpimd.so")
+RATES = os.path.join(HERE, "issue_rates")   # stand-alone measurement program
 SOURCES = ["capi.hip", "k_springs.hip", "k_pair.hip", "k_exchange.hip", "k_integrate.hip", "k_cycle_direct.hip", "k_init.hip", "k_persistent.hip"]
 ARCH = os.environ.get("PIMD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
@@ -42,8 +43,14 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link of libpimd.so failed")
     os.replace(tmp, OUT)
+    # the stand-alone issue-rate measurement (not part of the library)
+    cmd = ["hipcc", *FLAGS, "-o", RATES, os.path.join(CSRC, "issue_rates.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on issue_rates.hip")
     if verbose:
-        print(f"built {OUT}")
+        print(f"built {OUT} and {RATES}")
     return OUT
 
 

@@ -1,0 +1,167 @@
+// issue_rates.hip -- measures the issue cost of the instructions that bound the pair kernel.
+//
+// A standalone program (built next to the library as `issue_rates`), not part of libpimd.  Each
+// kernel fills the GPU (2048 workgroups of 256 threads, 8 waves per SIMD) with a loop of one
+// instruction kind carried by independent dependency chains, so that throughput, not latency,
+// sets its time; the time is converted to cycles per wave instruction and SIMD at the 2.4 GHz
+// peak engine clock (1024 SIMDs).  The kinds:
+//   fma      v_fma_f32 (no packed FP32: this build never forms packed FP32 instructions)
+//   exp      v_exp_f32 (exp2), the pair term's one transcendental
+//   mfma16   v_mfma_f32_16x16x4_f32 (1024 multiply-adds)
+//   mfma4    v_mfma_f32_4x4x1_16b_f32 (16 blocks, 256 multiply-adds)
+//   mix      four mfma4 and eight exp per iteration, independent of each other: if the matrix
+//            unit and the transcendental unit overlapped, this would cost max(), not the sum
+//   pair     the pair kernel's inner step for d = 2 (two differences, |d|^2 by one multiply and
+//            one FMA, one exp2, four FMAs for the forces on both particles), per pair
+// The results decide the pair kernel's design: whether a Gram-matrix formulation on the matrix
+// cores (|r_i - r_j|^2 = |r_i|^2 + |r_j|^2 - 2 r_i.r_j) can beat the plain vector form.
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdlib>
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+#define CK(x)                                                                     \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) {                                                       \
+      std::printf("HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+      std::exit(1);                                                               \
+    }                                                                             \
+  } while (0)
+
+constexpr int kBlocks = 2048, kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void k_fma(float* out, int iters) {
+  float v[8];
+  for (int q = 0; q < 8; ++q) v[q] = 0.1f * q + threadIdx.x * 1e-4f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = __builtin_fmaf(v[q], 0.999f, 1e-4f);
+  }
+  float s = 0.f;
+  for (int q = 0; q < 8; ++q) s += v[q];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_exp(float* out, int iters) {
+  float v[8];
+  for (int q = 0; q < 8; ++q) v[q] = 0.1f * q + threadIdx.x * 1e-4f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = __builtin_amdgcn_exp2f(-v[q]);   // stays in (0, 1]
+  }
+  float s = 0.f;
+  for (int q = 0; q < 8; ++q) s += v[q];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+template <int SHAPE>
+__global__ __launch_bounds__(kThreads) void k_mfma(float* out, int iters) {
+  f4 acc[4];
+  for (int q = 0; q < 4; ++q) acc[q] = (f4){0.f, 0.f, 0.f, 0.f};
+  const float a = 1e-3f * threadIdx.x, b = 2e-3f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (SHAPE == 16) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+      else acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc[q], 0, 0, 0);
+    }
+  }
+  float s = 0.f;
+  for (int q = 0; q < 4; ++q) s += acc[q][0] + acc[q][1] + acc[q][2] + acc[q][3];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_mix(float* out, int iters) {
+  f4 acc[4];
+  for (int q = 0; q < 4; ++q) acc[q] = (f4){0.f, 0.f, 0.f, 0.f};
+  float v[8];
+  for (int q = 0; q < 8; ++q) v[q] = 0.1f * q + threadIdx.x * 1e-4f;
+  const float a = 1e-3f * threadIdx.x, b = 2e-3f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc[q], 0, 0, 0);
+      v[2 * q] = __builtin_amdgcn_exp2f(-v[2 * q]);
+      v[2 * q + 1] = __builtin_amdgcn_exp2f(-v[2 * q + 1]);
+    }
+  }
+  float s = 0.f;
+  for (int q = 0; q < 4; ++q) s += acc[q][0] + acc[q][1] + acc[q][2] + acc[q][3];
+  for (int q = 0; q < 8; ++q) s += v[q];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// Eight partners per iteration; the particle's position moves with its accumulated force so
+// that nothing is loop-invariant, and the eight pairs of an iteration are independent.
+__global__ __launch_bounds__(kThreads) void k_pair(float* out, int iters) {
+  float xj[8][2], Fj[8][2];
+  for (int b = 0; b < 8; ++b) {
+    xj[b][0] = 0.37f * b - 1.1f + threadIdx.x * 1e-3f;
+    xj[b][1] = 0.21f * b - 0.7f;
+    Fj[b][0] = Fj[b][1] = 0.f;
+  }
+  float x0 = 0.05f, x1 = -0.03f, F0 = 0.f, F1 = 0.f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const float d0 = x0 - xj[b][0], d1 = x1 - xj[b][1];
+      float r2 = d0 * d0;
+      r2 = __builtin_fmaf(d1, d1, r2);
+      const float u = __builtin_amdgcn_exp2f(-r2);
+      F0 = __builtin_fmaf(u, d0, F0);
+      F1 = __builtin_fmaf(u, d1, F1);
+      Fj[b][0] = __builtin_fmaf(-u, d0, Fj[b][0]);
+      Fj[b][1] = __builtin_fmaf(-u, d1, Fj[b][1]);
+    }
+    x0 = __builtin_fmaf(F0, 1e-9f, x0);
+    x1 = __builtin_fmaf(F1, 1e-9f, x1);
+  }
+  float s = F0 + F1;
+  for (int b = 0; b < 8; ++b) s += Fj[b][0] + Fj[b][1];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+template <typename K>
+static double time_ms(K kern, float* out, int iters) {
+  hipEvent_t a, b;
+  CK(hipEventCreate(&a));
+  CK(hipEventCreate(&b));
+  hipLaunchKernelGGL(kern, dim3(kBlocks), dim3(kThreads), 0, 0, out, iters);   // warm-up
+  CK(hipGetLastError());
+  CK(hipDeviceSynchronize());
+  CK(hipEventRecord(a));
+  hipLaunchKernelGGL(kern, dim3(kBlocks), dim3(kThreads), 0, 0, out, iters);
+  CK(hipEventRecord(b));
+  CK(hipEventSynchronize(b));
+  float ms = 0.f;
+  CK(hipEventElapsedTime(&ms, a, b));
+  CK(hipEventDestroy(a));
+  CK(hipEventDestroy(b));
+  return ms;
+}
+
+int main() {
+  const int iters = 20000;
+  const double waves = kBlocks * (kThreads / 64.0), simds = 1024.0, hz = 2.4e9;
+  float* out = nullptr;
+  CK(hipMalloc(&out, sizeof(float) * kBlocks * kThreads));
+  // cycles per SIMD for `per_iter` units of the kind in every loop iteration of every wave
+  auto cycles = [&](double ms, double per_iter) { return ms * 1e-3 * hz * simds / (waves * iters * per_iter); };
+  double ms;
+  ms = time_ms(k_fma, out, iters);
+  std::printf("fma     %8.3f ms  %6.2f cycles per wave instruction\n", ms, cycles(ms, 8));
+  ms = time_ms(k_exp, out, iters);
+  std::printf("exp     %8.3f ms  %6.2f cycles per wave instruction\n", ms, cycles(ms, 8));
+  ms = time_ms(k_mfma<16>, out, iters);
+  std::printf("mfma16  %8.3f ms  %6.2f cycles per instruction\n", ms, cycles(ms, 4));
+  ms = time_ms(k_mfma<4>, out, iters);
+  std::printf("mfma4   %8.3f ms  %6.2f cycles per instruction\n", ms, cycles(ms, 4));
+  ms = time_ms(k_mix, out, iters);
+  std::printf("mix     %8.3f ms  %6.2f cycles per iteration (4 mfma4 + 8 exp)\n", ms, cycles(ms, 1));
+  ms = time_ms(k_pair, out, iters);
+  std::printf("pair    %8.3f ms  %6.2f cycles per 64 pairs (one wave step)\n", ms, cycles(ms, 8));
+  CK(hipFree(out));
+  return 0;
+}
