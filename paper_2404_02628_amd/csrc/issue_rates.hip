@@ -13,6 +13,9 @@
 //            unit and the transcendental unit overlapped, this would cost max(), not the sum
 //   pair     the pair kernel's inner step for d = 2 (two differences, |d|^2 by one multiply and
 //            one FMA, one exp2, four FMAs for the forces on both particles), per pair
+//   copy, copy4, triad   FP64 streams over 512 MiB arrays (y = x; z = x + s y) in two launch
+//            shapes: what a plain kernel gets out of HBM, for comparison with the memory-bound
+//            kernels (springs, integrator)
 // The results decide the pair kernel's design: whether a Gram-matrix formulation on the matrix
 // cores (|r_i - r_j|^2 = |r_i|^2 + |r_j|^2 - 2 r_i.r_j) can beat the plain vector form.
 #include <hip/hip_runtime.h>
@@ -123,6 +126,58 @@ __global__ __launch_bounds__(kThreads) void k_pair(float* out, int iters) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+__global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ x, double2* __restrict__ y, long long n2) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n2; i += (long long)gridDim.x * 256) y[i] = x[i];
+}
+
+// one workgroup per 4 x 256 double2: each thread moves four, all loads issued before the stores
+__global__ __launch_bounds__(256) void k_copy4(const double2* __restrict__ x, double2* __restrict__ y, long long n2) {
+  const long long base = blockIdx.x * 1024LL + threadIdx.x;
+  double2 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long i = base + 256LL * k;
+    v[k] = i < n2 ? x[i] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long i = base + 256LL * k;
+    if (i < n2) y[i] = v[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_triad(const double2* __restrict__ x, const double2* __restrict__ y,
+                                               double2* __restrict__ z, double s, long long n2) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n2; i += (long long)gridDim.x * 256) {
+    const double2 a = x[i], b = y[i];
+    z[i] = make_double2(a.x + s * b.x, a.y + s * b.y);
+  }
+}
+
+// best of five launches, in GB/s for `bytes` moved per launch
+template <typename L>
+static double stream_gbs(L launch, double bytes) {
+  hipEvent_t a, b;
+  CK(hipEventCreate(&a));
+  CK(hipEventCreate(&b));
+  launch();
+  CK(hipGetLastError());
+  CK(hipDeviceSynchronize());
+  float best = 1e30f;
+  for (int k = 0; k < 5; ++k) {
+    CK(hipEventRecord(a));
+    launch();
+    CK(hipEventRecord(b));
+    CK(hipEventSynchronize(b));
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, a, b));
+    if (ms < best) best = ms;
+  }
+  CK(hipEventDestroy(a));
+  CK(hipEventDestroy(b));
+  return bytes / (best * 1e-3) / 1e9;
+}
+
 template <typename K>
 static double time_ms(K kern, float* out, int iters) {
   hipEvent_t a, b;
@@ -163,5 +218,31 @@ int main() {
   ms = time_ms(k_pair, out, iters);
   std::printf("pair    %8.3f ms  %6.2f cycles per 64 pairs (one wave step)\n", ms, cycles(ms, 8));
   CK(hipFree(out));
+
+  const long long n = 64LL << 20;   // doubles per array: 512 MiB
+  double *x = nullptr, *y = nullptr, *z = nullptr;
+  CK(hipMalloc(&x, n * sizeof(double)));
+  CK(hipMalloc(&y, n * sizeof(double)));
+  CK(hipMalloc(&z, n * sizeof(double)));
+  CK(hipMemset(x, 0, n * sizeof(double)));
+  CK(hipMemset(y, 0, n * sizeof(double)));
+  const unsigned grid = 256 * 16;
+  const long long n2 = n / 2;
+  const double gc = stream_gbs([&] { hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, 0,
+                                                        (const double2*)x, (double2*)z, n2); },
+                               2.0 * n * sizeof(double));
+  std::printf("copy    %8.1f GB/s (read 512 MiB, write 512 MiB; 4096 workgroups, grid stride)\n", gc);
+  const unsigned grid4 = (unsigned)((n2 + 1023) / 1024);
+  const double gc4 = stream_gbs([&] { hipLaunchKernelGGL(k_copy4, dim3(grid4), dim3(256), 0, 0,
+                                                         (const double2*)x, (double2*)z, n2); },
+                                2.0 * n * sizeof(double));
+  std::printf("copy4   %8.1f GB/s (read 512 MiB, write 512 MiB; one workgroup per 16 KiB)\n", gc4);
+  const double gt = stream_gbs([&] { hipLaunchKernelGGL(k_triad, dim3(grid), dim3(256), 0, 0, (const double2*)x,
+                                                        (const double2*)y, (double2*)z, 0.5, n2); },
+                               3.0 * n * sizeof(double));
+  std::printf("triad   %8.1f GB/s (read 2 x 512 MiB, write 512 MiB)\n", gt);
+  CK(hipFree(x));
+  CK(hipFree(y));
+  CK(hipFree(z));
   return 0;
 }
