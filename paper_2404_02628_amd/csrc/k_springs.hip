@@ -50,48 +50,74 @@ __global__ __launch_bounds__(kSpringBlock) void k_springs(const RepDev* __restri
     const float kscale = R.pair_k;
     const int dp = shadow_dp(D);
     float* xsr = xs + R.shadow;
+    const long long PN = (long long)P * N;
+    // the shadow row of bead j holds all components of particle l: one vector store per bead
+    auto shadow = [&](int j, const double (&r)[D]) {
+      float* o = xsr + ((long long)j * R.npad + l) * dp;
+      if (D == 1) {
+        o[0] = (float)r[0] * kscale;
+      } else if (D == 2) {
+        *reinterpret_cast<float2*>(o) = make_float2((float)r[0] * kscale, (float)r[D > 1 ? 1 : 0] * kscale);
+      } else {
+        *reinterpret_cast<float4*>(o) = make_float4((float)r[0] * kscale, (float)r[D > 1 ? 1 : 0] * kscale,
+                                                    (float)r[D > 2 ? 2 : 0] * kscale, 0.f);
+      }
+    };
+    // beads 1 and 2 (P >= 2), every component
+    double rm[D], rc[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const double* xa = xr + (long long)a * P * N;
-      double* fa = fr + (long long)a * P * N;
-      double rm = xa[l];           // bead 1
-      double r0 = rm;
-      double rp = xa[(long long)N + l];  // bead 2 (exists since P >= 2)
+      rm[a] = xr[a * PN + l];
+      rc[a] = xr[a * PN + N + l];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double r0 = rm[a];
       a_out[(long long)a * R.npp + l] = r0;
-      fa[l] = -trap * r0;
+      fr[a * PN + l] = -trap * r0;
       ut += r0 * r0;
-      if (SHADOW) xsr[((long long)0 * R.npad + l) * dp + a] = (float)r0 * kscale;
-      double d = rp - r0;
+      const double d = rc[a] - r0;
       e_int += d * d;
-      double rc = rp;
-      // beads in chunks: the chunk's loads are issued together, so each chunk waits out one
-      // memory latency instead of one per bead (the sums keep their bead order)
-      for (int j0 = 1; j0 < P - 1; j0 += kBeadChunk) {
-        double nx[kBeadChunk];
+    }
+    if (SHADOW) shadow(0, rm);
+    // interior beads in chunks: the loads of a chunk (all components) are issued together, so
+    // each chunk waits out one memory latency (the sums keep their bead order per component)
+    for (int j0 = 1; j0 < P - 1; j0 += kBeadChunk) {
+      double nx[kBeadChunk][D];
 #pragma unroll
-        for (int u = 0; u < kBeadChunk; ++u) nx[u] = xa[(long long)min(j0 + u + 1, P - 1) * N + l];
+      for (int u = 0; u < kBeadChunk; ++u) {
+        const long long jn = (long long)min(j0 + u + 1, P - 1) * N + l;
 #pragma unroll
-        for (int u = 0; u < kBeadChunk; ++u) {
-          const int j = j0 + u;
-          if (j < P - 1) {
-            const double rn = nx[u];
-            fa[(long long)j * N + l] = -kap * (2.0 * rc - rn - rm) - trap * rc;
-            ut += rc * rc;
-            if (SHADOW) xsr[((long long)j * R.npad + l) * dp + a] = (float)rc * kscale;
-            const double dd = rn - rc;
+        for (int a = 0; a < D; ++a) nx[u][a] = xr[a * PN + jn];
+      }
+#pragma unroll
+      for (int u = 0; u < kBeadChunk; ++u) {
+        const int j = j0 + u;
+        if (j < P - 1) {
+          if (SHADOW) shadow(j, rc);
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const double rn = nx[u][a];
+            fr[a * PN + (long long)j * N + l] = -kap * (2.0 * rc[a] - rn - rm[a]) - trap * rc[a];
+            ut += rc[a] * rc[a];
+            const double dd = rn - rc[a];
             e_int += dd * dd;
-            rm = rc;
-            rc = rn;
+            rm[a] = rc[a];
+            rc[a] = rn;
           }
         }
       }
-      // rc is bead P
-      fa[(long long)(P - 1) * N + l] = -trap * rc;
-      ut += rc * rc;
-      if (SHADOW) xsr[((long long)(P - 1) * R.npad + l) * dp + a] = (float)rc * kscale;
-      b_out[(long long)a * R.npp + l] = rc;
-      if (l + 1 < N && l + 1 != R.na) {
-        double dl = rc - xa[l + 1];
+    }
+    // rc is bead P
+    if (SHADOW) shadow(P - 1, rc);
+    const bool has_link = l + 1 < N && l + 1 != R.na;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      fr[a * PN + (long long)(P - 1) * N + l] = -trap * rc[a];
+      ut += rc[a] * rc[a];
+      b_out[(long long)a * R.npp + l] = rc[a];
+      if (has_link) {
+        const double dl = rc[a] - xr[a * PN + l + 1];
         lk += dl * dl;
       }
     }
