@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define PIMD_ABI_VERSION 4
+#define PIMD_ABI_VERSION 5
 
 typedef enum {
     PIMD_OK = 0,
@@ -261,6 +261,15 @@ pimd_status pimd_debug_probs(pimd_ctx* ctx, int32_t r, double* G);
  * context's stream), copies excluded.  PIMD_ERR_STATE before any
  * pimd_set_state or pimd_init_system.  Synchronises. */
 pimd_status pimd_cycle_energies(pimd_ctx* ctx, int32_t r, double* E, double* ms);
+
+/* Not an operation of the method: a test hook for the failure path of the cooperative
+ * recursion schedule (one chain workgroup plus helper workgroups that hand each other work
+ * through device flags).  It raises the device error word, so that every wait of the next
+ * evaluation that finds its flag not yet set gives up at once, as a wait that ran out of polls
+ * would.  The kernels still run to their end, with invalid results.  The next getter that
+ * checks the word (pimd_get_forces, pimd_energies) returns PIMD_ERR_DEVICE, whatever the
+ * schedule, and clears it, after which evaluations are valid again.  Enqueued. */
+pimd_status pimd_debug_fail_waits(pimd_ctx* ctx);
 
 /* Per-kernel timing with HIP events on the stream each kernel is launched
  * on.  pimd_profile(ctx, 1) clears and enables, 0 disables.  pimd_kernel_times

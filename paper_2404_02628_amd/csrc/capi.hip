@@ -819,6 +819,13 @@ pimd_status pimd_synchronize(pimd_ctx* c) {
   return PIMD_OK;
 }
 
+pimd_status pimd_debug_fail_waits(pimd_ctx* c) {
+  if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
+  static const int one = 1;   // pageable source: the copy is staged before the call returns
+  HIPCHK(hipMemcpyAsync(c->w.err, &one, sizeof(int), hipMemcpyHostToDevice, c->s));
+  return PIMD_OK;
+}
+
 pimd_status pimd_graph_info(pimd_ctx* c, int32_t* state, int64_t* replays) {
   if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
   if (state) *state = c->graph_state;

@@ -32,7 +32,7 @@ EXPORTED = [
     "pimd_set_state", "pimd_get_state", "pimd_compute_forces", "pimd_get_forces", "pimd_step",
     "pimd_energies", "pimd_trace", "pimd_density", "pimd_reset_accumulators", "pimd_debug_potentials",
     "pimd_debug_probs", "pimd_profile", "pimd_kernel_times", "pimd_kernel_name", "pimd_synchronize",
-    "pimd_graph_info", "pimd_cycle_energies", "pimd_init_system",
+    "pimd_graph_info", "pimd_cycle_energies", "pimd_init_system", "pimd_debug_fail_waits",
 ]
 
 
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
         "pimd_graph_info": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "pimd_cycle_energies": (C.c_int, [_vp, C.c_int32, _dp, _dp]),
         "pimd_init_system": (C.c_int, [_vp, _dp, C.POINTER(C.c_uint64)]),
+        "pimd_debug_fail_waits": (C.c_int, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -244,6 +245,10 @@ def pimd_synchronize(h):
     _chk(load().pimd_synchronize(h), "pimd_synchronize")
 
 
+def pimd_debug_fail_waits(h):
+    _chk(load().pimd_debug_fail_waits(h), "pimd_debug_fail_waits")
+
+
 def pimd_graph_info(h):
     """(state, replays): state 0 not built, 1 replayed, 2 not requested, 3 capture failed."""
     st, n = C.c_int32(), C.c_int64()
@@ -364,6 +369,9 @@ class Context:
 
     def graph_info(self):
         return pimd_graph_info(self.h)
+
+    def debug_fail_waits(self):
+        pimd_debug_fail_waits(self.h)
 
     def close(self):
         if getattr(self, "h", None) is not None:

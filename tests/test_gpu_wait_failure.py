@@ -1,0 +1,41 @@
+"""Failure path of the cooperative recursion schedule, forced from the host.
+
+The chain workgroup and its helpers hand each other work through device flags, and every wait
+on a flag gives up after a bounded number of polls, raising a device error word instead of
+hanging.  `debug_fail_waits` raises that word before an evaluation, so every wait that finds
+its flag not yet set gives up at once (no kernel waits out its poll limit and nothing hangs).
+The getter must then report PIMD_ERR_DEVICE, and the next evaluation must be valid again: the
+same forces as before the failure, bit for bit (the schedule's arithmetic is deterministic)."""
+import numpy as np
+import pytest
+
+from paper_2404_02628_amd.workloads import System, random_positions
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("helpers", [3, 8])
+def test_failed_waits_are_reported_and_cleared(helpers):
+    from paper_2404_02628_amd.pimd import Context, PimdError, PIMD_ERR_DEVICE
+    s = System(n=400, p=8, dim=2, beta=2.0, xi=1.0, pair_amp=1.0, pair_width=0.5, sigma=1.5, seed=61)
+    x = random_positions(s.n, s.p, s.dim, s.sigma, s.seed)
+    print(f"wait failure: N={s.n}, one chain + {helpers} helpers", flush=True)
+    ctx = Context([s], precision="fp64", recursion_workgroups=helpers + 1)
+    try:
+        ctx.set_state(0, x)
+        ctx.compute_forces()
+        f_ref = ctx.forces(0)
+        assert np.all(np.isfinite(f_ref))
+        ctx.debug_fail_waits()
+        ctx.compute_forces()
+        with pytest.raises(PimdError) as e:
+            ctx.forces(0)
+        assert e.value.code == PIMD_ERR_DEVICE
+        assert "timed out" in str(e.value)
+        ctx.compute_forces()
+        f = ctx.forces(0)
+        assert np.array_equal(f, f_ref)
+        en = ctx.energies(0)
+        assert np.isfinite(en["e_prim"])
+    finally:
+        ctx.close()
