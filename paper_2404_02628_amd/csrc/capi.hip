@@ -466,7 +466,7 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
     int dev = 0, cus = 0, coop = 0;
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop) {
-      const int per_cu = recursion_coop_max_blocks_per_cu(c->pl.d.D);
+      const int per_cu = recursion_coop_max_blocks_per_cu(c->pl.d.D, c->pl.d.maxn);
       const long long nchains = 2LL * c->pl.d.R;
       const long long capacity = (long long)per_cu * cus;
       int max_nblk = 0;
