@@ -35,9 +35,9 @@
 // factors, adds Pr[l -> l+1] = -expm1(G^f_l + G^b_{N-l} - G^f_N - beta link_l) (Eq. 13) and forms
 // the end-bead forces of Eqs. 15-16.  The N^2/2 probabilities are never stored or recomputed.
 //
-// Recursion schedule (one workgroup per replica and direction, eight wavefronts).  Rows are
+// Recursion schedule (one workgroup per replica and direction, four wavefronts).  Rows are
 // processed in blocks of 64 (lane = row).  For a block: (0) a reference R_i = the largest term of
-// the previous block's columns (a lower bound of the row's largest earlier term); (1) the eight
+// the previous block's columns (a lower bound of the row's largest earlier term); (1) the four
 // waves sum exp(term - R_i) and its weighted payloads over all earlier columns (if a term ever
 // exceeds R_i by more than the double range, that wave redoes its columns with a running
 // maximum); (2) wave 0 runs a max-plus pass over the in-block columns giving each row a scale D_i
@@ -696,6 +696,8 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
 // already finished (panel c = the columns of block c), so the chain itself only adds the panel
 // it has just produced (from LDS).  Helper h owns row blocks 2+h, 2+h+H, ...; for its block b it
 // folds in panels 0..b-2 as they are published and then publishes the partial sums of block b.
+// The chain has eight wavefronts; from 64 row blocks on it is pipelined: the previous block's
+// in-block payloads and row averages are formed by waves 2.. during wave 0's serial passes.
 // Flags hold the epoch of the launch that set them, so they never need clearing.  All workgroups
 // are launched cooperatively (co-resident), every wait depends only on work earlier in the chain,
 // and every wait gives up after a bounded number of polls (raising an error word) instead of
