@@ -186,8 +186,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(replicas and slices would shard over GPUs, see DESIGN.md); use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (independent "
+              "replicas, or the imaginary-time slices of one replica, would shard over GPUs); use --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -5,7 +5,7 @@
 // instruction kind carried by independent dependency chains, so that throughput, not latency,
 // sets its time; the time is converted to cycles per wave instruction and SIMD at the 2.4 GHz
 // peak engine clock (1024 SIMDs).  The kinds:
-//   fma      v_fma_f32 (no packed FP32: this build never forms packed FP32 instructions)
+//   fma      v_fma_f32 (compiled with packed FP32 disabled, as the library is)
 //   exp      v_exp_f32 (exp2), the pair term's one transcendental
 //   mfma16   v_mfma_f32_16x16x4_f32 (1024 multiply-adds)
 //   mfma4    v_mfma_f32_4x4x1_16b_f32 (16 blocks, 256 multiply-adds)

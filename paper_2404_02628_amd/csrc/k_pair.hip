@@ -10,12 +10,14 @@
 //
 // Mixed precision: coordinates come from the FP32 shadow, pre-scaled by sqrt(log2 e)/s, so a
 // term is exp2(-|dr|^2) (one v_exp_f32); FP32 sums run over runs of kFold partners and are then
-// folded into FP64 accumulators.  FP64 mode reads the FP64 positions and uses exp().
+// folded into FP64 accumulators.  FP64 mode reads the FP64 positions and uses the branch-free table
+// exponential of fast_exp.h (at most 2 ulp).
 //
 // Estimator sums (only when requested): sum over ordered pairs of u and of u |dr|^2, giving
 // U_pair and the pair part of the virial W = sum_pairs u (1 - r^2/s^2).
 #include "pimd_internal.h"
 #include "device_util.h"
+#include "fast_exp.h"
 
 namespace pimd {
 
@@ -116,6 +118,9 @@ __global__ __launch_bounds__(256) void k_pair_f64(const RepDev* __restrict__ rep
                                                   double* __restrict__ pairpart, int P) {
   constexpr int IT = 4 / JS;
   __shared__ double red[4][D + 2][64];
+  __shared__ double tab[kExpTable];   // table of the branch-free exponential (2 ulp)
+  if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
+  __syncthreads();
   const int g = xcd_work_index((int)blockIdx.x, (int)gridDim.x);
   const int4 wk = work[g];
   const RepDev& R = reps[wk.x];
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(256) void k_pair_f64(const RepDev* __restrict__ rep
       d[a] = xi[a] - xr[((long long)a * P + slice) * N + j] * inv_s;
       r2 = fma(d[a], d[a], r2);
     }
-    double u = exp(-r2);
+    double u = fast_exp(-r2, tab);
 #pragma unroll
     for (int a = 0; a < D; ++a) F[a] = fma(u, d[a], F[a]);
     if (EST) {
