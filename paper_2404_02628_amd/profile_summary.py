@@ -11,6 +11,10 @@
         (copy-mib MiB read and written), and the traffic record of the named kernel (mean
         counter values, scales, and the SHA-256 of the sources that define the kernel, so a
         reader can tell whether the record still describes the current code).
+
+    python -m paper_2404_02628_amd.profile_summary pmc DIR [--kernel PREFIX ...]
+        mean value per dispatch of every counter of one --pmc run, for the kernels whose short
+        name starts with a given prefix
 """
 from __future__ import annotations
 
@@ -136,6 +140,38 @@ def counters(fetch_dir, write_dir, copy_mib, kernel, replicas, precision):
     return "\n".join(lines), rec
 
 
+def _named_counter_rows(d: str):
+    """(kernel name, grid threads, counter name, value) per dispatch and counter."""
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += [(r["Kernel_Name"], int(r["Grid_Size"]), r["Counter_Name"], float(r["Counter_Value"]))
+                 for r in csv.DictReader(open(path))]
+    if not rows:
+        import sqlite3
+        for path in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
+            con = sqlite3.connect(path)
+            rows += [(n, int(g), c, float(v)) for n, g, c, v in
+                     con.execute("select kernel_name, grid_size, counter_name, value from counters_collection")]
+    return rows
+
+
+def pmc(d: str, kernels):
+    """Mean value per dispatch of every collected counter, for the kernels whose short name starts
+    with one of `kernels`."""
+    g = defaultdict(lambda: defaultdict(list))
+    for name, grid, cname, value in _named_counter_rows(d):
+        k = short_name(name)
+        if any(k.startswith(p) for p in kernels):
+            g[(k, grid)][cname].append(value)
+    lines = []
+    for (k, grid), cs in sorted(g.items()):
+        lines += [f"`{k}` (grid {grid} threads)", "", "| counter | dispatches | mean per dispatch |", "|---|---:|---:|"]
+        lines += [f"| {c} | {len(v)} | {statistics.fmean(v):.6g} |" for c, v in sorted(cs.items())]
+        lines.append("")
+    return "\n".join(lines)
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -148,9 +184,14 @@ def main(argv=None) -> int:
     c.add_argument("--kernel", default="k_pair_f32")
     c.add_argument("--replicas", type=int, default=64)
     c.add_argument("--precision", default="mixed")
+    m = sub.add_parser("pmc")
+    m.add_argument("dir")
+    m.add_argument("--kernel", action="append", default=[])
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace(a.dir))
+    elif a.cmd == "pmc":
+        print(pmc(a.dir, a.kernel or ["k_"]))
     else:
         table, rec = counters(a.fetch_dir, a.write_dir, a.copy_mib, a.kernel, a.replicas, a.precision)
         print(table)
