@@ -211,7 +211,8 @@ static void launch_pair_js(const Dims& d, const DevPtrs& w, int js, hipStream_t 
 // eight i-positions and eight j-positions of a lane stay in registers and each term feeds both
 // sides: F_i += u d and F_j -= u d (Newton's third law per slice), with per-lane accumulators
 // indexed by a and by b.  After the tile pair, a transpose through LDS sums the eight lanes
-// that share a particle (reduce-scatter: lane L ends with the total of particle L of the tile),
+// that share a particle (reduce-scatter: lane L = c0 + 8 k0 ends with the total of particle L of
+// tile I and of particle k0 + 8 c0 of tile J, which keeps the J side's reads on distinct banks),
 // and the totals are added to the slice's FP64 forces in LDS.  Tile pairs are scheduled as a
 // round-robin tournament (circle method): within a round no two tile pairs share a tile, so
 // the LDS force updates need no atomics and their order is fixed (results are reproducible).
@@ -278,11 +279,13 @@ __device__ inline void sym_tile_pair(const float* __restrict__ pos, double* __re
     for (int k = 0; k < 8; ++k) si += red[(c0 + 8 * k) * kRedStride + k0];
 #pragma unroll
     for (int b = 0; b < 8; ++b) red[lane * kRedStride + b] = Fj[b][c];
+    // lane (c0, k0) sums particle k0 + 8 c0 of tile J over the eight lanes that share k0 (rows
+    // q + 8 k0, column c0: distinct banks across each half wave)
     float sj = 0.f;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sj += red[(q + 8 * c0) * kRedStride + k0];
+    for (int q = 0; q < 8; ++q) sj += red[(q + 8 * k0) * kRedStride + c0];
     Fs[c * npad + I * 64 + lane] += (double)si;
-    Fs[c * npad + J * 64 + lane] += (double)sj;
+    Fs[c * npad + J * 64 + k0 + 8 * c0] += (double)sj;
   }
 }
 
