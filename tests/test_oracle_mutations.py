@@ -43,6 +43,13 @@ MUTATIONS = {
     "philox round count": ("for (int round = 0; round < 10; ++round) {", "for (int round = 0; round < 9; ++round) {"),
     "philox word order": ("uint32_t n1 = (uint32_t)p1;", "uint32_t n1 = (uint32_t)p0;"),
     "Box-Muller radius": ("double rad = sqrt(-2.0 * log(u1));", "double rad = sqrt(-log(u1));"),
+    # the continuum factor z(k beta) for every cycle longer than one ring, planted alike in the
+    # log-domain and the signed routine so that they still agree with each other
+    "finite-P cycle factor z(k beta) for k >= 2": [
+        ("            double kb = (double)k * B;\n            /* ln z(kB)",
+         "            double kb = k == 1 ? B : (double)k * beta;\n            /* ln z(kB)"),
+        ("double q = exp(-(double)k * B);", "double q = exp(-(double)k * (k == 1 ? B : beta));"),
+    ],
 }
 
 
@@ -50,12 +57,14 @@ MUTATIONS = {
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_pins_fail_on_planted_mistake(name):
     src = open(os.path.join(ROOT, "oracle", "pimd_oracle.c")).read()
-    old, new = MUTATIONS[name]
-    assert src.count(old) == 1, f"mutation anchor not found: {name}"
+    edits = MUTATIONS[name]
+    for old, new in ([edits] if isinstance(edits, tuple) else edits):
+        assert src.count(old) == 1, f"mutation anchor not found: {name}"
+        src = src.replace(old, new)
     with tempfile.TemporaryDirectory() as d:
         csrc = os.path.join(d, "pimd_oracle.c")
         with open(csrc, "w") as fh:
-            fh.write(src.replace(old, new))
+            fh.write(src)
         with open(os.path.join(d, "pimd_oracle.h"), "w") as fh:
             fh.write(open(os.path.join(ROOT, "oracle", "pimd_oracle.h")).read())
         lib = os.path.join(d, "liboracle.so")
@@ -64,6 +73,6 @@ def test_pins_fail_on_planted_mistake(name):
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             "tests/test_oracle_pins.py", "tests/test_golden_paper.py",
                             "tests/test_oracle_fermions.py", "tests/test_oracle_species.py",
-                            "tests/test_oracle_init.py"],
+                            "tests/test_oracle_init.py", "tests/test_oracle_finite_p_exact.py"],
                            cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode != 0, f"pins did not catch: {name}\n{r.stdout[-2000:]}"
