@@ -1,6 +1,8 @@
 """Builds libpimd.so (HIP, gfx950) in-tree with hipcc.
 
 Usage: python -m paper_2404_02628_amd.build   (or call build()).
+       python -m paper_2404_02628_amd.build --issue-rates   builds only the stand-alone
+       instruction issue-rate program (measure/issue_rates.hip), which is not part of the library.
 """
 from __future__ import annotations
 
@@ -12,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpimd.so")
-RATES = os.path.join(HERE, "issue_rates")   # stand-alone measurement program
+RATES = os.path.join(HERE, "measure", "issue_rates")   # stand-alone measurement program
 SOURCES = ["capi.hip", "k_springs.hip", "k_pair.hip", "k_exchange.hip", "k_integrate.hip", "k_cycle_direct.hip", "k_init.hip", "k_persistent.hip"]
 ARCH = os.environ.get("PIMD_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
@@ -43,16 +45,25 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link of libpimd.so failed")
     os.replace(tmp, OUT)
-    # the stand-alone issue-rate measurement (not part of the library)
-    cmd = ["hipcc", *FLAGS, "-o", RATES, os.path.join(CSRC, "issue_rates.hip")]
+    if verbose:
+        print(f"built {OUT}")
+    return OUT
+
+
+def build_issue_rates(verbose: bool = False) -> str:
+    """The stand-alone issue-rate measurement program (not part of the library)."""
+    cmd = ["hipcc", *FLAGS, "-o", RATES, os.path.join(HERE, "measure", "issue_rates.hip")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed on issue_rates.hip")
     if verbose:
-        print(f"built {OUT} and {RATES}")
-    return OUT
+        print(f"built {RATES}")
+    return RATES
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--issue-rates" in sys.argv[1:]:
+        build_issue_rates(verbose=True)
+    else:
+        build(verbose=True)

@@ -1,6 +1,6 @@
 // issue_rates.hip -- measures the issue cost of the instructions that bound the pair kernel.
 //
-// A standalone program (built next to the library as `issue_rates`), not part of libpimd.  Each
+// A standalone program (`python -m paper_2404_02628_amd.build --issue-rates`), not part of libpimd.  Each
 // kernel fills the GPU (2048 workgroups of 256 threads, 8 waves per SIMD) with a loop of one
 // instruction kind carried by independent dependency chains, so that throughput, not latency,
 // sets its time; the time is converted to cycles per wave instruction and SIMD at the 2.4 GHz
