@@ -33,6 +33,20 @@
  *   index out of range, parameters outside their domain) give
  *   PIMD_ERR_INVALID and leave the context unchanged.  HIP runtime failures
  *   give PIMD_ERR_DEVICE.
+ * - Failures inside enqueued work are recorded on the device and reported by
+ *   the next call that synchronises (pimd_synchronize, pimd_get_state,
+ *   pimd_get_forces, pimd_energies, pimd_trace, pimd_density), after that call
+ *   has written its outputs:
+ *     PIMD_ERR_NONFINITE  a force, momentum or position of some replica became
+ *                         non-finite; pimd_last_error() names the lowest such
+ *                         replica;
+ *     PIMD_ERR_DEVICE     a wait of the cooperative recursion schedule timed
+ *                         out (pimd_config.recursion_workgroups).
+ *   Either halts the run on the device from the pass that detected it on: the
+ *   integrator, the estimators, the trace and the density histogram stop
+ *   writing, so the state stays at the step where the failure appeared.  Once
+ *   a call has reported it, pimd_step and pimd_compute_forces return
+ *   PIMD_ERR_STATE until pimd_set_state or pimd_init_system restarts the run.
  */
 #ifndef PIMD_H
 #define PIMD_H
@@ -78,6 +92,13 @@ typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
                                      of every replica (one workgroup each, state on chip) in one
                                      launch per 4096 steps; its pair term is FP64 in both
                                      precision modes; for tuning and testing                 */
+#define PIMD_FLAG_LONGEST_FIRST 8 /* dispatch the per-replica work of the pair kernel and of the batched
+                                     recursion longest replica first (descending N) instead of in
+                                     replica order; a packing choice for batches of uneven N      */
+#define PIMD_FLAG_PAIR_SPLIT_1 16 /* waves per 64-particle tile of the ordered pair kernel: the value
+                                     (flags & PIMD_FLAG_PAIR_SPLIT_MASK) / PIMD_FLAG_PAIR_SPLIT_1 is
+                                     0 (chosen from the work size), 1, 2 or 3 (1, 2 or 4 waves)    */
+#define PIMD_FLAG_PAIR_SPLIT_MASK 48
 
 /* One independent system (replica).  Units are free; the paper uses
  * hbar = m = omega = k_B = 1 (Sec. IV.A). */
@@ -177,11 +198,16 @@ pimd_status pimd_init_system(pimd_ctx* ctx, const double* pos_sigma, const uint6
  * nhc (optional) holds the thermostat state as [2][nhc_len][dim][P][N]
  * (positions eta, then velocities v_eta); NULL zeroes it (p NULL zeroes p).
  * `where` says whether the pointers are host or device memory.  Invalidates the
- * forces of replica r until the next evaluation.  Synchronous. */
+ * forces of replica r until the next evaluation, and restarts a halted run
+ * (a replica that is still non-finite halts it again at the next evaluation).
+ * Together with pimd_get_state this is a checkpoint: a context of the same
+ * configuration given every replica's x, p and nhc continues the trajectory
+ * bit for bit.  Synchronous. */
 pimd_status pimd_set_state(pimd_ctx* ctx, int32_t r, const double* x, const double* p,
                            const double* nhc, pimd_mem where);
 
-/* Copies the state of replica r out (any pointer may be NULL).  Synchronous. */
+/* Copies the state of replica r out (any pointer may be NULL).  Synchronous.
+ * Reports a halted run (PIMD_ERR_NONFINITE, PIMD_ERR_DEVICE) after copying. */
 pimd_status pimd_get_state(pimd_ctx* ctx, int32_t r, double* x, double* p, double* nhc,
                            pimd_mem where);
 
@@ -200,7 +226,8 @@ pimd_status pimd_get_forces(pimd_ctx* ctx, int32_t r, double* f, pimd_mem where)
  * x += p dt/m', F = force(x), p += F dt/2, NHC(dt/2).  The estimators, the
  * density histogram and the trace are taken every `sample_every` steps
  * (0 = never).  The first call evaluates the forces of the initial state.
- * Enqueued only.  Errors: PIMD_ERR_INVALID (n_steps < 0, sample_every < 0).
+ * Enqueued only.  Errors: PIMD_ERR_INVALID (n_steps < 0, sample_every < 0),
+ * PIMD_ERR_STATE (the run is halted, see the conventions above).
  * When every replica has N <= 64 and dim*P*N <= 512 (and PIMD_FLAG_NO_PERSISTENT
  * is not set) the steps run in the persistent kernel: one launch per 4096 steps,
  * one workgroup per replica with its state on chip, FP64 pair term in both
@@ -266,9 +293,9 @@ pimd_status pimd_cycle_energies(pimd_ctx* ctx, int32_t r, double* E, double* ms)
  * recursion schedule (one chain workgroup plus helper workgroups that hand each other work
  * through device flags).  It raises the device error word, so that every wait of the next
  * evaluation that finds its flag not yet set gives up at once, as a wait that ran out of polls
- * would.  The kernels still run to their end, with invalid results.  The next getter that
- * checks the word (pimd_get_forces, pimd_energies) returns PIMD_ERR_DEVICE, whatever the
- * schedule, and clears it, after which evaluations are valid again.  Enqueued. */
+ * would.  The kernels still run to their end, with invalid results.  The next call that
+ * synchronises returns PIMD_ERR_DEVICE, whatever the schedule; the run is then halted (see the conventions above) until pimd_set_state or
+ * pimd_init_system lowers the word, after which evaluations are valid again.  Enqueued. */
 pimd_status pimd_debug_fail_waits(pimd_ctx* ctx);
 
 /* Per-kernel timing with HIP events on the stream each kernel is launched
@@ -281,7 +308,8 @@ pimd_status pimd_kernel_times(pimd_ctx* ctx, double* ms, int64_t* launches, int3
                               int32_t* n_kinds);
 const char* pimd_kernel_name(int32_t kind);
 
-/* Waits for all work enqueued by the context. */
+/* Waits for all work enqueued by the context; reports a halted run (PIMD_ERR_NONFINITE,
+ * PIMD_ERR_DEVICE). */
 pimd_status pimd_synchronize(pimd_ctx* ctx);
 
 #ifdef __cplusplus

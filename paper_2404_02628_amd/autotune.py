@@ -2,9 +2,11 @@
 
 For a fixed set of replicas the knobs are the recursion schedule (`recursion_workgroups`: 0 lets
 the library choose, 1 forces one workgroup per replica and direction, k > 1 a cooperative chain
-with k-1 helpers), the pair kernel (the symmetric per-slice kernel where the library would pick
-it, or the ordered one), replay of steady steps from a HIP graph, and, for replicas small enough
-(N <= 64, d P N <= 512), the persistent kernel that runs whole steps on chip.  `tune` times every
+with k-1 helpers), the pair kernel and its work granularity (the symmetric per-slice kernel where
+the library would pick it, or the ordered one with 1, 2 or 4 waves per 64-particle tile), the
+packing of uneven replicas (work dispatched in replica order or longest replica first), replay of
+steady steps from a HIP graph, and, for replicas small enough (N <= 64, d P N <= 512), the
+persistent kernel that runs whole steps on chip.  `tune` times every
 candidate for a few MD steps on the device and returns the fastest; `tune_replicas` picks the
 batch size (replica count) with the highest aggregate replica-steps/s.  Both measure, so they
 need a GPU; `candidates` and `pick` are plain functions that tests exercise without one.
@@ -33,10 +35,13 @@ class Knobs:
     pair_kernel: str = "auto"
     graphs: bool = False
     persistent: bool = False
+    order: str = "index"      # "index" or "longest": dispatch order of the per-replica work
+    pair_split: int = 0       # waves per tile of the ordered pair kernel (0: chosen by the library)
 
     def as_kwargs(self) -> Dict:
         return {"recursion_workgroups": self.recursion_workgroups, "pair_kernel": self.pair_kernel,
-                "graphs": self.graphs, "persistent": self.persistent}
+                "graphs": self.graphs, "persistent": self.persistent, "order": self.order,
+                "pair_split": self.pair_split}
 
 
 @dataclass
@@ -56,21 +61,27 @@ def candidates(systems: Sequence[System], precision: str, graphs: bool = False) 
     if len(systems) <= 8 and nblk > 2:
         # a few cooperative helper counts between "one helper" and "as many as fit"
         scheds += sorted({h + 1 for h in (1, 4, 16, 32, 64, 128) if h < nblk - 1})
-    pairs = ["auto", "ordered"] if (has_pair and precision == "mixed" and
-                                    sum(s.p for s in systems if s.pair_amp > 0) >= 256) else ["auto"]
+    sym = has_pair and precision == "mixed" and sum(s.p for s in systems if s.pair_amp > 0) >= 256
+    # pair kernel and granularity: the library's choice, and where the symmetric kernel would run
+    # also the ordered one at each tile split; the FP64 ordered kernel at each split
+    pairs = [("auto", 0)]
+    if has_pair:
+        pairs += [("ordered", k) for k in (1, 2, 4)] if sym else [("auto", k) for k in (1, 2, 4)]
+    orders = ["index", "longest"] if len({s.n for s in systems}) > 1 else ["index"]
     out = [Knobs(persistent=True)] if persistent_fits(systems) else []
     for r in scheds:
-        for pk in pairs:
-            for g in ((False, True) if graphs else (False,)):
-                out.append(Knobs(r, pk, g))
+        for pk, split in pairs:
+            for o in orders:
+                for g in ((False, True) if graphs else (False,)):
+                    out.append(Knobs(r, pk, g, False, o, split))
     return out
 
 
 def pick(timings: Dict[Knobs, float]) -> Knobs:
     """Fastest candidate; ties go to the simpler one (library defaults first)."""
     def simplicity(k: Knobs):
-        return (not k.persistent, k.graphs, k.pair_kernel != "auto", k.recursion_workgroups != 0,
-                k.recursion_workgroups)
+        return (not k.persistent, k.graphs, k.pair_kernel != "auto", k.pair_split != 0, k.order != "index",
+                k.recursion_workgroups != 0, k.recursion_workgroups)
     return min(timings, key=lambda k: (timings[k], simplicity(k)))
 
 

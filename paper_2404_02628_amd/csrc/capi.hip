@@ -41,6 +41,10 @@ const char* kKindNames[K_COUNT] = {"springs", "pair", "recursion", "exchange_for
                                    "integrate_second", "integrate_fused", "estimators", "density",
                                    "persistent_steps"};
 
+// LDS one workgroup may hold on gfx950 (160 KiB per compute unit): the symmetric pair kernel keeps a
+// whole slice there, which bounds the N it serves (6,400 particles in 2-D, 3,840 in 3-D, 12,864 in 1-D).
+constexpr int kMaxLdsBytes = 160 * 1024;
+
 // Steps per launch of the persistent kernel (a call with more steps is split).
 constexpr long long kPersistChunk = 4096;
 
@@ -49,10 +53,13 @@ long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 struct Plan {
   Dims d{};
   int jsplit = 1;
+  int ipw = 0;               // particles per pair work item (1 << 30: the whole slice)
+  RepDev rep0{};             // constants of replica 0 (also when the lists are not stored)
   bool persistent = false;   // every replica fits one workgroup: steps run in the persistent kernel
   int persist_maxdof = 0;
   std::vector<RepDev> reps;
   std::vector<int4> springwork, pairwork, intwork;
+  std::vector<int> reporder;  // replica of each recursion workgroup pair, in launch order
   size_t off[32]{};
   size_t total = 0;
 };
@@ -60,13 +67,30 @@ struct Plan {
 enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LINK, S_EINT, S_GF, S_GB, S_COLREC, S_AVG,
            S_FLAGS, S_PARTIAL, S_ERR,
            S_SPRINGP, S_PAIRP, S_REDP, S_REC, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_SPRINGW, S_PAIRW, S_INTW, S_DBG,
-           S_COUNT };
+           S_REPORD, S_COUNT };
 
 // Doubles of the debug scratch: two potential arrays, up to 2^20 entries of a dense N x N table
 // (filled in row chunks), or two parameters per replica for the seeded initial state.
 long long dbg_doubles(int maxn, int R) {
   return std::max<long long>(std::max<long long>(2LL * (maxn + 2), 2LL * R),
                              std::min<long long>((long long)maxn * maxn, 1LL << 20));
+}
+
+// Checks one replica's parameters (the message is only built on failure).
+pimd_status validate_replica(const pimd_replica& q, int r) {
+  auto bad = [r](const char* what) { return fail(PIMD_ERR_INVALID, "replica " + std::to_string(r) + ": " + what); };
+  if (q.n < 1 || q.n > (1 << 20)) return bad("n must be in 1..2^20");
+  if (q.n2 < 0 || q.n2 >= q.n) return bad("n2 must be in 0..n-1");
+  if (!(q.beta > 0) || !std::isfinite(q.beta)) return bad("beta must be > 0");
+  if (!(q.hbar > 0) || !std::isfinite(q.hbar)) return bad("hbar must be > 0");
+  if (!(q.mass > 0) || !std::isfinite(q.mass)) return bad("mass must be > 0");
+  if (!(q.omega >= 0) || !std::isfinite(q.omega)) return bad("omega must be >= 0");
+  if (!(q.xi >= 0 && q.xi <= 1)) return bad("xi must be in [0, 1]");
+  if (!(q.pair_amp >= 0) || !std::isfinite(q.pair_amp)) return bad("pair_amp must be >= 0");
+  if (q.pair_amp > 0 && (!(q.pair_width > 0) || !std::isfinite(q.pair_width))) return bad("pair_width must be > 0");
+  if (!(q.dt > 0) || !std::isfinite(q.dt)) return bad("dt must be > 0");
+  if (!std::isfinite(q.nhc_q) || !std::isfinite(q.bead_mass)) return bad("non-finite nhc_q/bead_mass");
+  return PIMD_OK;
 }
 
 pimd_status validate(const pimd_config* c) {
@@ -84,28 +108,22 @@ pimd_status validate(const pimd_config* c) {
   if (c->trace_capacity < 0) return fail(PIMD_ERR_INVALID, "trace_capacity must be >= 0");
   if (c->recursion_workgroups < 0 || c->recursion_workgroups > 4096)
     return fail(PIMD_ERR_INVALID, "recursion_workgroups must be in 0..4096");
-  if ((c->flags & ~(PIMD_FLAG_GRAPH | PIMD_FLAG_PAIR_ORDERED | PIMD_FLAG_NO_PERSISTENT)) != 0)
+  if ((c->flags & ~(PIMD_FLAG_GRAPH | PIMD_FLAG_PAIR_ORDERED | PIMD_FLAG_NO_PERSISTENT | PIMD_FLAG_LONGEST_FIRST |
+                    PIMD_FLAG_PAIR_SPLIT_MASK)) != 0)
     return fail(PIMD_ERR_INVALID, "unknown bits in flags");
   for (int r = 0; r < c->n_replicas; ++r) {
-    const pimd_replica& q = c->replicas[r];
-    std::string where = "replica " + std::to_string(r) + ": ";
-    if (q.n < 1 || q.n > (1 << 20)) return fail(PIMD_ERR_INVALID, where + "n must be in 1..2^20");
-    if (q.n2 < 0 || q.n2 >= q.n) return fail(PIMD_ERR_INVALID, where + "n2 must be in 0..n-1");
-    if (!(q.beta > 0) || !std::isfinite(q.beta)) return fail(PIMD_ERR_INVALID, where + "beta must be > 0");
-    if (!(q.hbar > 0) || !std::isfinite(q.hbar)) return fail(PIMD_ERR_INVALID, where + "hbar must be > 0");
-    if (!(q.mass > 0) || !std::isfinite(q.mass)) return fail(PIMD_ERR_INVALID, where + "mass must be > 0");
-    if (!(q.omega >= 0) || !std::isfinite(q.omega)) return fail(PIMD_ERR_INVALID, where + "omega must be >= 0");
-    if (!(q.xi >= 0 && q.xi <= 1)) return fail(PIMD_ERR_INVALID, where + "xi must be in [0, 1]");
-    if (!(q.pair_amp >= 0) || !std::isfinite(q.pair_amp)) return fail(PIMD_ERR_INVALID, where + "pair_amp must be >= 0");
-    if (q.pair_amp > 0 && (!(q.pair_width > 0) || !std::isfinite(q.pair_width)))
-      return fail(PIMD_ERR_INVALID, where + "pair_width must be > 0");
-    if (!(q.dt > 0) || !std::isfinite(q.dt)) return fail(PIMD_ERR_INVALID, where + "dt must be > 0");
-    if (!std::isfinite(q.nhc_q) || !std::isfinite(q.bead_mass)) return fail(PIMD_ERR_INVALID, where + "non-finite nhc_q/bead_mass");
+    const pimd_status st = validate_replica(c->replicas[r], r);
+    if (st != PIMD_OK) return st;
   }
   return PIMD_OK;
 }
 
-void make_plan(const pimd_config* c, Plan& pl) {
+// Plans the workspace of a configuration: per-replica constants, work lists and segment offsets.
+// With lists = false (the no-allocation entry point) nothing is stored on the heap: the work
+// lists are only counted (their entries follow from the counts, see the prepare kernel), the
+// first replica's constants go to pl.rep0, and the segments that the evaluation of one replica
+// does not need (state it takes from the caller, thermostat, trace, density, debug) are empty.
+void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
   Dims& d = pl.d;
   d.R = c->n_replicas; d.P = c->p; d.D = c->dim; d.M = c->nhc_len; d.precision = c->precision;
   d.sy_order = c->sy_order; d.bins = c->density_bins; d.cap = c->trace_capacity; d.rmax = c->density_rmax;
@@ -121,16 +139,20 @@ void make_plan(const pimd_config* c, Plan& pl) {
       pair_slices += d.P;
       pair_maxn = std::max(pair_maxn, c->replicas[r].n);
     }
-  const bool sym = d.precision == PIMD_MIXED && pair_slices >= 256 && pair_sym_lds_bytes(d.D, pair_maxn) <= 65536 &&
+  const bool sym = d.precision == PIMD_MIXED && pair_slices >= 256 && pair_sym_lds_bytes(d.D, pair_maxn) <= kMaxLdsBytes &&
                    (c->flags & PIMD_FLAG_PAIR_ORDERED) == 0;
-  pl.jsplit = sym ? 0 : (tiles64 < 1024 ? 4 : (tiles64 < 2048 ? 2 : 1));
+  const int split_code = (c->flags & PIMD_FLAG_PAIR_SPLIT_MASK) / PIMD_FLAG_PAIR_SPLIT_1;   // 0, 1, 2, 3
+  const int forced_split = split_code == 0 ? 0 : (1 << (split_code - 1));                   // 0, 1, 2, 4
+  pl.jsplit = sym ? 0 : (forced_split ? forced_split : (tiles64 < 1024 ? 4 : (tiles64 < 2048 ? 2 : 1)));
   const int ipw = sym ? (1 << 30) : 64 * (4 / pl.jsplit);  // particles per pair workgroup
+  pl.ipw = ipw;
   long long G = 0, NP = 0, XS = 0;
+  long long nspring = 0, npair = 0, nint = 0;
   int maxn = 0;
-  pl.reps.resize(d.R);
+  if (lists) pl.reps.resize(d.R);
   for (int r = 0; r < d.R; ++r) {
     const pimd_replica& q = c->replicas[r];
-    RepDev& R = pl.reps[r];
+    RepDev R;
     std::memset(&R, 0, sizeof(R));
     R.n = q.n;
     R.npad = (int)round_up(q.n, kTile);
@@ -161,16 +183,38 @@ void make_plan(const pimd_config* c, Plan& pl) {
     R.dt_mp = q.dt / R.mp;
     R.trap_p = R.mw2 / (double)d.P;
     R.pair_k = (float)(q.pair_amp > 0 ? std::sqrt(1.4426950408889634) / q.pair_width : 1.0);
-    R.spw0 = (long long)pl.springwork.size();
-    for (int l0 = 0; l0 < q.n; l0 += kSpringBlock) pl.springwork.push_back(make_int4(r, l0, 0, 0));
-    R.spw1 = (long long)pl.springwork.size();
+    R.spw0 = nspring;
+    for (int l0 = 0; l0 < q.n; l0 += kSpringBlock, ++nspring)
+      if (lists) pl.springwork.push_back(make_int4(r, l0, 0, 0));
+    R.spw1 = nspring;
     R.rw0 = R.spw0; R.rw1 = R.spw1;
-    R.pw0 = (long long)pl.pairwork.size();
+    for (long long d0 = 0; d0 < R.ndof; d0 += kIntBlock, ++nint)
+      if (lists) pl.intwork.push_back(make_int4(r, (int)d0, 0, 0));
+    if (lists) pl.reps[r] = R;
+    if (r == 0) pl.rep0 = R;
+  }
+  // Launch order of the per-replica work of the pair kernel and the batched recursion: replica
+  // index order, or longest first (descending N, ties by index) so that the most expensive
+  // workgroups are dispatched first and the short ones fill in behind them.
+  const bool longest = (c->flags & PIMD_FLAG_LONGEST_FIRST) != 0;
+  if (lists) {
+    pl.reporder.resize(d.R);
+    for (int r = 0; r < d.R; ++r) pl.reporder[r] = r;
+    if (longest)
+      std::stable_sort(pl.reporder.begin(), pl.reporder.end(),
+                       [c](int a, int b) { return c->replicas[a].n > c->replicas[b].n; });
+  }
+  // pair work items, one contiguous range per replica
+  for (int k = 0; k < d.R; ++k) {
+    const int r = lists ? pl.reporder[k] : k;
+    const pimd_replica& q = c->replicas[r];
+    long long pw0 = npair;
     if (q.pair_amp > 0)
       for (int j = 0; j < d.P; ++j)
-        for (int i0 = 0; i0 < q.n; i0 += ipw) pl.pairwork.push_back(make_int4(r, j, i0, 0));
-    R.pw1 = (long long)pl.pairwork.size();
-    for (long long d0 = 0; d0 < R.ndof; d0 += kIntBlock) pl.intwork.push_back(make_int4(r, (int)d0, 0, 0));
+        for (int i0 = 0; i0 < q.n; i0 += ipw, ++npair)
+          if (lists) pl.pairwork.push_back(make_int4(r, j, i0, 0));
+    if (lists) { pl.reps[r].pw0 = pw0; pl.reps[r].pw1 = npair; }
+    if (r == 0) { pl.rep0.pw0 = pw0; pl.rep0.pw1 = npair; }
   }
   d.G = G; d.NPtot = NP; d.XStot = XS; d.maxn = maxn; d.pair_maxn = pair_maxn;
   // small replicas: whole steps in one persistent launch (unless the caller asks otherwise)
@@ -180,10 +224,10 @@ void make_plan(const pimd_config* c, Plan& pl) {
     pl.persistent = pl.persistent && persistent_fits(d.D, d.P, c->replicas[r].n);
     pl.persist_maxdof = std::max(pl.persist_maxdof, d.D * d.P * c->replicas[r].n);
   }
-  d.nspringwg = (long long)pl.springwork.size();
-  d.npairwork = (long long)pl.pairwork.size();
+  d.nspringwg = nspring;
+  d.npairwork = npair;
   d.nreducewg = d.nspringwg;
-  d.nintwg = (long long)pl.intwork.size();
+  d.nintwg = nint;
   // segment sizes in bytes
   size_t sz[S_COUNT];
   sz[S_REPS] = sizeof(RepDev) * d.R;
@@ -209,6 +253,9 @@ void make_plan(const pimd_config* c, Plan& pl) {
   sz[S_PAIRW] = sizeof(int4) * std::max<long long>(d.npairwork, 1);
   sz[S_INTW] = sizeof(int4) * d.nintwg;
   sz[S_DBG] = 8ull * dbg_doubles(maxn, d.R);
+  sz[S_REPORD] = sizeof(int) * d.R;
+  if (!lists)
+    for (int k : {S_X, S_P, S_F, S_ETA, S_VETA, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_DBG}) sz[k] = 0;
   size_t o = 0;
   for (int s = 0; s < S_COUNT; ++s) {
     pl.off[s] = o;
@@ -228,6 +275,7 @@ struct pimd_ctx {
   bool forces_valid = false;
   bool evaluated = false;
   bool has_state = false;   // some replica's positions were set
+  bool halted = false;      // a status word was seen raised: no steps until set_state / init_system
   long long step = 0;
   bool has_pair = false;
   int helpers = 0;       // helper workgroups per recursion chain (0: one workgroup per chain)
@@ -360,16 +408,41 @@ hipMemcpyKind kind_out(pimd_mem m) { return m == PIMD_DEVICE ? hipMemcpyDeviceTo
 
 }  // namespace
 
-static pimd_status check_device_error(pimd_ctx* c) {
-  int e = 0;
-  HIPCHK(hipMemcpyAsync(&e, c->w.err, sizeof(int), hipMemcpyDeviceToHost, c->s));
+// Reads the device status words (after the work enqueued so far).  A timed-out wait of the
+// cooperative recursion gives PIMD_ERR_DEVICE, a non-finite force, momentum or position
+// PIMD_ERR_NONFINITE naming the lowest such replica.  Either halts the context: the kernels have
+// stopped advancing the state, and pimd_step / pimd_compute_forces refuse to run until
+// pimd_set_state or pimd_init_system lowers the words.
+static pimd_status check_status(pimd_ctx* c) {
+  int st[3] = {0, 0, 0};
+  HIPCHK(hipMemcpyAsync(st, c->w.err, sizeof(st), hipMemcpyDeviceToHost, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
-  if (e != 0) {
-    int z = 0;
-    HIPCHK(hipMemcpyAsync(c->w.err, &z, sizeof(int), hipMemcpyHostToDevice, c->s));
-    HIPCHK(hipStreamSynchronize(c->s));
-    return fail(PIMD_ERR_DEVICE, "a wait of the cooperative exchange recursion timed out; results are invalid");
+  if (st[0] != 0) {
+    c->halted = true;
+    c->forces_valid = false;
+    return fail(PIMD_ERR_DEVICE, "a wait of the cooperative exchange recursion timed out; results are invalid "
+                                 "and the run is halted until pimd_set_state or pimd_init_system");
   }
+  if (st[2] != 0) {
+    c->halted = true;
+    return fail(PIMD_ERR_NONFINITE, "replica " + std::to_string(kNonfiniteBase - st[2]) +
+                                        ": non-finite force, momentum or position; the run is halted at the step "
+                                        "where it appeared until pimd_set_state or pimd_init_system");
+  }
+  return PIMD_OK;
+}
+
+// Lowers the wait-failure and non-finite words (the evaluation stamp between them is kept).
+static pimd_status clear_status(pimd_ctx* c) {
+  HIPCHK(hipMemsetAsync(c->w.err, 0, sizeof(int), c->s));
+  HIPCHK(hipMemsetAsync(c->w.err + 2, 0, sizeof(int), c->s));
+  c->halted = false;
+  return PIMD_OK;
+}
+
+static pimd_status check_not_halted(pimd_ctx* c) {
+  if (c->halted)
+    return fail(PIMD_ERR_STATE, "the run is halted after a failure; call pimd_set_state or pimd_init_system");
   return PIMD_OK;
 }
 
@@ -436,6 +509,7 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   w.reducework = w.springwork;
   w.intwork = (int4*)(c->ws + off[S_INTW]);
   w.dbg = (double*)(c->ws + off[S_DBG]);
+  w.reporder = (int*)(c->ws + off[S_REPORD]);
   for (auto& r : c->pl.reps) c->has_pair = c->has_pair || r.amp > 0;
   c->graph_state = (cfg->flags & PIMD_FLAG_GRAPH) ? 0 : 2;
   auto cleanup = [&](pimd_status s2) {
@@ -454,6 +528,8 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
     e = hipMemcpyAsync(w.pairwork, c->pl.pairwork.data(), sizeof(int4) * c->pl.pairwork.size(), hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess && !c->pl.intwork.empty())
     e = hipMemcpyAsync(w.intwork, c->pl.intwork.data(), sizeof(int4) * c->pl.intwork.size(), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(w.reporder, c->pl.reporder.data(), sizeof(int) * c->pl.reporder.size(), hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->sc, hipStreamNonBlocking);
@@ -514,6 +590,7 @@ pimd_status pimd_set_state(pimd_ctx* c, int32_t r, const double* x, const double
   const Dims& d = c->pl.d;
   const size_t nb = sizeof(double) * (size_t)R.ndof;
   HIPCHK(hipStreamSynchronize(c->s));
+  if ((st = clear_status(c)) != PIMD_OK) return st;
   HIPCHK(hipMemcpyAsync(c->w.x + R.dof, x, nb, kind_in(where), c->s));
   if (p) HIPCHK(hipMemcpyAsync(c->w.p + R.dof, p, nb, kind_in(where), c->s));
   else HIPCHK(hipMemsetAsync(c->w.p + R.dof, 0, nb, c->s));
@@ -547,12 +624,14 @@ pimd_status pimd_get_state(pimd_ctx* c, int32_t r, double* x, double* p, double*
       HIPCHK(hipMemcpyAsync(nhc + (size_t)(d.M + k) * R.ndof, c->w.veta + (long long)k * d.G + R.dof, nb, kind_out(where), c->s));
     }
   HIPCHK(hipStreamSynchronize(c->s));
-  return PIMD_OK;
+  return check_status(c);
 }
 
 pimd_status pimd_compute_forces(pimd_ctx* c) {
   if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
-  pimd_status st = evaluate(c, true, c->s);
+  pimd_status st = check_not_halted(c);
+  if (st != PIMD_OK) return st;
+  st = evaluate(c, true, c->s);
   if (st != PIMD_OK) return st;
   RUN(K_INT2, c->s, launch_integrate_second(c->pl.d, c->w, false, c->s));
   st = sample(c, false);
@@ -567,18 +646,18 @@ pimd_status pimd_get_forces(pimd_ctx* c, int32_t r, double* f, pimd_mem where) {
   if (st != PIMD_OK) return st;
   if (!f) return fail(PIMD_ERR_INVALID, "f is NULL");
   if (!c->forces_valid) return fail(PIMD_ERR_STATE, "no force evaluation since the last set_state");
-  if ((st = check_device_error(c)) != PIMD_OK) return st;
   const RepDev& R = c->pl.reps[r];
   HIPCHK(hipMemcpyAsync(f, c->w.f + R.dof, sizeof(double) * (size_t)R.ndof, kind_out(where), c->s));
   HIPCHK(hipStreamSynchronize(c->s));
-  return PIMD_OK;
+  return check_status(c);
 }
 
 pimd_status pimd_step(pimd_ctx* c, int64_t n_steps, int32_t sample_every) {
   if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
   if (n_steps < 0 || sample_every < 0) return fail(PIMD_ERR_INVALID, "n_steps and sample_every must be >= 0");
   const Dims& d = c->pl.d;
-  pimd_status st;
+  pimd_status st = check_not_halted(c);
+  if (st != PIMD_OK) return st;
   if (c->pl.persistent) {
     bool need = !c->forces_valid;
     for (long long done = 0; done < n_steps; done += kPersistChunk) {
@@ -642,12 +721,12 @@ pimd_status pimd_energies(pimd_ctx* c, int32_t r, pimd_estimates* out) {
   pimd_status st = check_ctx_r(c, r);
   if (st != PIMD_OK) return st;
   if (!out) return fail(PIMD_ERR_INVALID, "out is NULL");
-  if ((st = check_device_error(c)) != PIMD_OK) return st;
   double o[kRec];
   HIPCHK(hipMemcpyAsync(o, c->w.rec + (long long)kRec * r, sizeof(o), hipMemcpyDeviceToHost, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
+  if (o[kValid] == 1.0) rec_to_struct(o, out);
+  if ((st = check_status(c)) != PIMD_OK) return st;
   if (o[kValid] != 1.0) return fail(PIMD_ERR_STATE, "no sampled evaluation yet");
-  rec_to_struct(o, out);
   for (int k = 0; k < kStep; ++k)
     if (!std::isfinite(o[k])) return fail(PIMD_ERR_NONFINITE, "replica " + std::to_string(r) + ": non-finite estimator");
   return PIMD_OK;
@@ -673,7 +752,7 @@ pimd_status pimd_trace(pimd_ctx* c, int32_t r, pimd_estimates* out, int64_t max_
     }
   }
   *n_samples = take;
-  return PIMD_OK;
+  return check_status(c);
 }
 
 pimd_status pimd_density(pimd_ctx* c, int32_t r, uint64_t* counts, int64_t* n_samples) {
@@ -686,7 +765,7 @@ pimd_status pimd_density(pimd_ctx* c, int32_t r, uint64_t* counts, int64_t* n_sa
   HIPCHK(hipMemcpyAsync(&ns, c->w.denssamples + r, sizeof(ns), hipMemcpyDeviceToHost, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
   *n_samples = ns;
-  return PIMD_OK;
+  return check_status(c);
 }
 
 pimd_status pimd_reset_accumulators(pimd_ctx* c) {
@@ -742,6 +821,8 @@ pimd_status pimd_init_system(pimd_ctx* c, const double* pos_sigma, const uint64_
     std::memcpy(&prm[2 * r + 1], &seeds[r], sizeof(double));
   }
   HIPCHK(hipStreamSynchronize(c->s));
+  pimd_status st = clear_status(c);
+  if (st != PIMD_OK) return st;
   HIPCHK(hipMemcpyAsync(c->w.dbg, prm.data(), sizeof(double) * prm.size(), hipMemcpyHostToDevice, c->s));
   HIPCHK(launch_init_state(c->pl.d, c->w, c->w.dbg, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
@@ -816,7 +897,7 @@ const char* pimd_kernel_name(int32_t kind) {
 pimd_status pimd_synchronize(pimd_ctx* c) {
   if (!c) return fail(PIMD_ERR_INVALID, "context is NULL");
   HIPCHK(hipStreamSynchronize(c->s));
-  return PIMD_OK;
+  return check_status(c);
 }
 
 pimd_status pimd_debug_fail_waits(pimd_ctx* c) {

@@ -591,16 +591,18 @@ struct Prefetch {
   }
 };
 
-// One workgroup per replica and direction (batched replicas fill the machine).
+// One workgroup per replica and direction (batched replicas fill the machine).  Workgroups 2k
+// and 2k + 1 serve replica order[k]: the plan lists replicas in index order or longest first.
 template <int D>
 __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __restrict__ reps,
                                                            const double* __restrict__ ends,
                                                            const double* __restrict__ link,
                                                            double* __restrict__ gf, double* __restrict__ gb,
                                                            double4* __restrict__ colrec,
-                                                           double* __restrict__ avg) {
+                                                           double* __restrict__ avg,
+                                                           const int* __restrict__ order) {
   __shared__ RecShared<D, kBatchWaves> sh;
-  const int rep = blockIdx.x >> 1, dir = blockIdx.x & 1;
+  const int rep = order[blockIdx.x >> 1], dir = blockIdx.x & 1;
   const RepDev& R = reps[rep];
   const int N = R.n;
   const RecMap<D> mp = rec_map<D>(R, ends, link, dir);
@@ -962,7 +964,8 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
 
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s) {
   dim3 grid((unsigned)(2 * d.R)), block(64 * kBatchWaves);
-#define L(DD) hipLaunchKernelGGL(k_recursion<DD>, grid, block, 0, s, w.reps, w.ends, w.link, w.gf, w.gb, w.colrec, w.avg)
+#define L(DD) hipLaunchKernelGGL(k_recursion<DD>, grid, block, 0, s, w.reps, w.ends, w.link, w.gf, w.gb, w.colrec, w.avg, \
+                              w.reporder)
   switch (d.D) {
     case 1: L(1); break;
     case 2: L(2); break;

@@ -20,12 +20,15 @@ namespace pimd {
 // mode 1: second half (F = F + F_pair, then p += F dt/2, NHC(dt/2))
 // mode 2: F = F + F_pair only (force evaluation without integration)
 // mode 3: second half of this step fused with the first half of the next one
+// A thread whose force, momentum or new position is not finite raises the non-finite status
+// word; once a status word is raised no integrator pass writes anything.
 template <int M, int MODE>
 __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restrict__ reps,
                                                          const int4* __restrict__ work, double* __restrict__ x,
                                                          double* __restrict__ p, double* __restrict__ f,
                                                          const double* __restrict__ fpair, double* __restrict__ eta,
-                                                         double* __restrict__ veta, long long G, SyW sy) {
+                                                         double* __restrict__ veta, long long G, SyW sy,
+                                                         int* status) {
   __shared__ double tab[kExpTable];
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
@@ -44,6 +47,7 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
   const double fpv = kPair ? fpair[gi] : 0.0;
   double pv = kP ? p[gi] : 0.0;
   const double xv = kX ? x[gi] : 0.0;
+  const bool halted = status_halted(status);
   double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
 #pragma unroll
   for (int k = 0; k < (M > 0 ? M : 1); ++k) {
@@ -54,26 +58,34 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
     if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
     __syncthreads();
   }
-  if (!ok) return;
+  if (!ok || halted) return;
   if (kPair) fv = R.amp > 0.0 ? fv + fpv : fv;
   if (MODE == 0) {
     if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
     pv += hdt * fv;
-    x[gi] = xv + R.dt_mp * pv;
+    const double xn = xv + R.dt_mp * pv;
+    if (!isfinite(fv) || !isfinite(xn)) status_nonfinite(status, wk.x);
+    x[gi] = xn;
     p[gi] = pv;
   } else {
     // the total force is kept for readers of the last evaluation; in the fused pass the next
     // evaluation overwrites it unread
     if (MODE != 3) f[gi] = fv;
-    if (MODE == 2) return;
+    if (MODE == 2) {
+      if (!isfinite(fv)) status_nonfinite(status, wk.x);
+      return;
+    }
     pv += hdt * fv;
     if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    double xn = 0.0;
     if (MODE == 3) {
       // second thermostat half-step of this step and first of the next, chain in registers
       if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
       pv += hdt * fv;
-      x[gi] = xv + R.dt_mp * pv;
+      xn = xv + R.dt_mp * pv;
+      x[gi] = xn;
     }
+    if (!isfinite(fv) || !isfinite(pv) || !isfinite(xn)) status_nonfinite(status, wk.x);
     p[gi] = pv;
   }
   if (kChain) {
@@ -92,8 +104,12 @@ __global__ __launch_bounds__(256) void k_estimators(const RepDev* __restrict__ r
                                                     const double* __restrict__ reducepart, double* __restrict__ rec,
                                                     double* __restrict__ trace, long long* __restrict__ tracecount,
                                                     long long G, int M, int D, int P, int cap, long long step,
-                                                    int record) {
+                                                    int record, const int* status) {
   __shared__ double lds[2 * 4];
+  __shared__ int halted;
+  if (threadIdx.x == 0) halted = status_halted(status) ? 1 : 0;
+  __syncthreads();
+  if (halted) return;   // a halted run records nothing more
   const int r = blockIdx.x;
   const RepDev& R = reps[r];
   double acc[2] = {0.0, 0.0};
@@ -158,8 +174,13 @@ __global__ __launch_bounds__(256) void k_estimators(const RepDev* __restrict__ r
 template <int D>
 __global__ __launch_bounds__(256) void k_density(const RepDev* __restrict__ reps, const int4* __restrict__ work,
                                                  const double* __restrict__ x, unsigned long long* __restrict__ dens,
-                                                 long long* __restrict__ nsamp, int P, int bins, double rmax) {
+                                                 long long* __restrict__ nsamp, int P, int bins, double rmax,
+                                                 const int* status) {
   extern __shared__ unsigned int hist[];
+  __shared__ int halted;
+  if (threadIdx.x == 0) halted = status_halted(status) ? 1 : 0;
+  __syncthreads();
+  if (halted) return;   // a halted run records nothing more
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
   const int N = R.n;
@@ -211,7 +232,7 @@ static hipError_t launch_integrate_mode(const Dims& d, const DevPtrs& w, hipStre
   dim3 grid((unsigned)d.nintwg), block(kIntBlock);
   const SyW sy = sy_weights(d.sy_order);
 #define L(MM) hipLaunchKernelGGL((k_integrate<MM, MODE>), grid, block, 0, s, w.reps, w.intwork, w.x, w.p, w.f, \
-                                 w.fpair, w.eta, w.veta, d.G, sy)
+                                 w.fpair, w.eta, w.veta, d.G, sy, w.err)
   switch (d.M) {
     case 0: L(0); break; case 1: L(1); break; case 2: L(2); break; case 3: L(3); break;
     case 4: L(4); break; case 5: L(5); break; case 6: L(6); break; case 7: L(7); break; case 8: L(8); break;
@@ -236,7 +257,7 @@ hipError_t launch_integrate_fused(const Dims& d, const DevPtrs& w, hipStream_t s
 hipError_t launch_estimators(const Dims& d, const DevPtrs& w, long long step, bool record, hipStream_t s) {
   hipLaunchKernelGGL(k_estimators, dim3(d.R), dim3(256), 0, s, w.reps, w.p, w.eta, w.veta, w.gf, w.springpart,
                      w.pairpart, w.reducepart, w.rec, w.trace, w.tracecount, d.G, d.M, d.D, d.P, d.cap, step,
-                     record ? 1 : 0);
+                     record ? 1 : 0, w.err);
   return hipGetLastError();
 }
 
@@ -245,9 +266,9 @@ hipError_t launch_density(const Dims& d, const DevPtrs& w, hipStream_t s) {
   dim3 grid((unsigned)d.nspringwg), block(256);
   size_t sh = sizeof(unsigned int) * (size_t)(d.bins + 1);
   switch (d.D) {
-    case 1: hipLaunchKernelGGL(k_density<1>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax); break;
-    case 2: hipLaunchKernelGGL(k_density<2>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax); break;
-    case 3: hipLaunchKernelGGL(k_density<3>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax); break;
+    case 1: hipLaunchKernelGGL(k_density<1>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax, w.err); break;
+    case 2: hipLaunchKernelGGL(k_density<2>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax, w.err); break;
+    case 3: hipLaunchKernelGGL(k_density<3>, grid, block, sh, s, w.reps, w.springwork, w.x, w.dens, w.denssamples, d.P, d.bins, d.rmax, w.err); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

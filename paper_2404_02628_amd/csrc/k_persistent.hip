@@ -41,6 +41,7 @@ struct PersistShared {
   double fe[2][D][kPMaxN];                 // end-bead exchange forces: bead 1, bead P
   double part[kPMaxN][4];                  // per-particle trap, S and pair partial sums
   double red[8 * kPMaxWaves];
+  int halt;                                // a status word was raised before the launch
 };
 
 struct PersistArgs {
@@ -49,6 +50,7 @@ struct PersistArgs {
   double* ends; double* link; double* eint; double* gf; double* gb;
   double* rec; double* trace; long long* tracecount;
   unsigned long long* dens; long long* denssamples;
+  int* status;
   long long G;
   int P, cap, bins, sample_every, need_forces;
   double rmax;
@@ -250,6 +252,7 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
   const long long gi = R.dof + t;
   const long long G = A.G;
   if (t < kExpTable) sh.tab[t] = exp_table_entry(t);
+  if (t == 0) sh.halt = status_halted(A.status) ? 1 : 0;
   double xv = 0.0, pv = 0.0, fv = 0.0, e[M > 0 ? M : 1], v[M > 0 ? M : 1];
 #pragma unroll
   for (int k = 0; k < (M > 0 ? M : 1); ++k) { e[k] = 0.0; v[k] = 0.0; }
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
     for (int k = 0; k < M; ++k) { e[k] = A.eta[k * G + gi]; v[k] = A.veta[k * G + gi]; }
   }
   __syncthreads();
+  if (sh.halt) return;   // a halted run advances no further (uniform over the workgroup)
   double en[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (A.need_forces) fv = persist_evaluate<D>(sh, R, P, t, own, ca, cj, cl, xv, false, en);
   const double hdt = 0.5 * R.dt;
@@ -334,8 +338,9 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
       __syncthreads();   // the next evaluation rewrites the positions in LDS
     }
   }
-  // state and the last evaluation back to the workspace
+  // state and the last evaluation back to the workspace; a non-finite value raises the status word
   if (own) {
+    if (!isfinite(xv) || !isfinite(pv) || !isfinite(fv)) status_nonfinite(A.status, r);
     A.x[gi] = xv;
     A.p[gi] = pv;
     A.f[gi] = fv;
@@ -370,6 +375,7 @@ hipError_t launch_persistent(const Dims& d, const DevPtrs& w, int maxdof, long l
   A.ends = w.ends; A.link = w.link; A.eint = w.eint; A.gf = w.gf; A.gb = w.gb;
   A.rec = w.rec; A.trace = w.trace; A.tracecount = w.tracecount;
   A.dens = w.dens; A.denssamples = w.denssamples;
+  A.status = w.err;
   A.G = d.G;
   A.P = d.P; A.cap = d.cap; A.bins = d.bins; A.sample_every = sample_every; A.need_forces = need_forces ? 1 : 0;
   A.rmax = d.rmax;

@@ -63,7 +63,10 @@ struct DevPtrs {
   double* avg;                 // [2][dim+1][npp] per replica: weighted row averages of the recursions
   int* flags;                  // [4][npp] per replica: panel / partial ready flags (epochs), per direction
   double* partial;             // [2][dim+3][npp] per replica: helper partial sums (m, s, payloads)
-  int* err;                    // error word raised by a timed-out wait
+  int* err;                    // status words: [0] raised by a timed-out wait of the cooperative
+                               // recursion, [1] evaluation stamp (advanced by the spring kernel),
+                               // [2] non-finite word: kNonfiniteBase - r of the lowest replica r
+                               // whose force, momentum or position was found non-finite (0: none)
   double* springpart;          // [nspringwg][4]
   double* pairpart;            // [npairwork][2]
   double* reducepart;          // [nreducewg][2]
@@ -76,6 +79,7 @@ struct DevPtrs {
   int4* pairwork;              // {rep, slice, i0, 0}
   int4* reducework;            // {rep, l0, 0, 0}
   int4* intwork;               // {rep, first dof, 0, 0}
+  int* reporder;               // [R] replica of the k-th recursion workgroup pair (launch order)
   double* dbg;                 // debug scratch (N+2 doubles of the largest replica, x2)
 };
 
@@ -91,6 +95,18 @@ struct Dims {
 };
 
 __host__ __device__ inline int shadow_dp(int D) { return D == 3 ? 4 : D; }
+
+constexpr int kNonfiniteBase = 0x7fffffff;
+
+// A raised status word halts the dynamics: the integrator, the estimators and the density stop
+// writing, so the state and the accumulators stay as they were when the failure was detected.
+__device__ inline bool status_halted(const int* err) {
+  return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+         __hip_atomic_load(err + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Records that replica r produced a non-finite value (the lowest such replica wins).
+__device__ inline void status_nonfinite(int* err, int r) { atomicMax(err + 2, kNonfiniteBase - r); }
 
 // Launchers (one per translation unit).
 hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s);

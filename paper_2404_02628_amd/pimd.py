@@ -26,6 +26,9 @@ PIMD_HOST, PIMD_DEVICE = 0, 1
 PIMD_FLAG_GRAPH = 1
 PIMD_FLAG_PAIR_ORDERED = 2
 PIMD_FLAG_NO_PERSISTENT = 4
+PIMD_FLAG_LONGEST_FIRST = 8
+PIMD_FLAG_PAIR_SPLIT_1 = 16
+PIMD_FLAG_PAIR_SPLIT_MASK = 48
 
 EXPORTED = [
     "pimd_abi_version", "pimd_last_error", "pimd_workspace_bytes", "pimd_create", "pimd_destroy",
@@ -268,13 +271,18 @@ class Context:
     def __init__(self, systems: Sequence[System], precision: str = "mixed", nhc_len: Optional[int] = None,
                  sy_order: int = 3, density_bins: int = 64, density_rmax: float = 6.0, trace_capacity: int = 0,
                  recursion_workgroups: int = 0, graphs: bool = False, pair_kernel: str = "auto",
-                 persistent: bool = True, device: str = "cuda:0"):
+                 persistent: bool = True, order: str = "index", pair_split: int = 0, device: str = "cuda:0"):
         import torch  # device memory and streams only
 
         if not systems:
             raise ValueError("need at least one system")
         if pair_kernel not in ("auto", "ordered"):
             raise ValueError("pair_kernel must be 'auto' or 'ordered'")
+        if order not in ("index", "longest"):
+            raise ValueError("order must be 'index' or 'longest'")
+        split_code = {0: 0, 1: 1, 2: 2, 4: 3}.get(pair_split)
+        if split_code is None:
+            raise ValueError("pair_split must be 0 (automatic), 1, 2 or 4")
         p, dim = systems[0].p, systems[0].dim
         if any(s.p != p or s.dim != dim for s in systems):
             raise ValueError("all replicas of one context share P and dim")
@@ -292,7 +300,9 @@ class Context:
                                sy_order, density_bins, trace_capacity, recursion_workgroups,
                                (PIMD_FLAG_GRAPH if graphs else 0) |
                                (PIMD_FLAG_PAIR_ORDERED if pair_kernel == "ordered" else 0) |
-                               (0 if persistent else PIMD_FLAG_NO_PERSISTENT), density_rmax, reps)
+                               (0 if persistent else PIMD_FLAG_NO_PERSISTENT) |
+                               (PIMD_FLAG_LONGEST_FIRST if order == "longest" else 0) |
+                               split_code * PIMD_FLAG_PAIR_SPLIT_1, density_rmax, reps)
         self.nbytes = pimd_workspace_bytes(self.cfg)
         self.device = torch.device(device)
         with torch.cuda.device(self.device):

@@ -20,6 +20,26 @@ def test_candidates_cover_the_schedules_that_apply():
     assert len(set(candidates(batched_systems(64, 505), "mixed"))) == len(candidates(batched_systems(64, 505), "mixed"))
 
 
+def test_candidates_cover_packing_and_pair_granularity():
+    uneven = candidates(batched_systems(64, 505), "mixed")
+    assert {k.order for k in uneven} == {"index", "longest"}               # uneven N: both packings
+    assert {(k.pair_kernel, k.pair_split) for k in uneven} == {("auto", 0), ("ordered", 1), ("ordered", 2),
+                                                               ("ordered", 4)}
+    even = candidates([WORKLOADS["large_gauss"].with_(seed=k) for k in range(16)], "mixed")
+    assert {k.order for k in even} == {"index"}                            # equal N: order is moot
+    fp64 = candidates([WORKLOADS["large_gauss"]], "fp64")
+    assert {k.pair_split for k in fp64} == {0, 1, 2, 4}                    # ordered FP64 kernel splits
+    ideal = candidates([WORKLOADS["huge_ideal_10k"]], "fp64")
+    assert {k.pair_split for k in ideal} == {0}                            # no pair term: nothing to split
+
+
+def test_pick_prefers_library_defaults_for_packing():
+    t = {Knobs(order="longest"): 1.0, Knobs(): 1.0, Knobs(pair_split=2): 1.0}
+    assert pick(t) == Knobs()
+    t = {Knobs(order="longest"): 0.9, Knobs(): 1.0}
+    assert pick(t) == Knobs(order="longest")
+
+
 def test_pick_takes_the_fastest_and_breaks_ties_toward_defaults():
     t = {Knobs(0, "auto", False): 2.0, Knobs(1, "ordered", True): 1.0, Knobs(5, "auto", False): 3.0}
     assert pick(t) == Knobs(1, "ordered", True)

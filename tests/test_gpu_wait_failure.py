@@ -4,8 +4,10 @@ The chain workgroup and its helpers hand each other work through device flags, a
 on a flag gives up after a bounded number of polls, raising a device error word instead of
 hanging.  `debug_fail_waits` raises that word before an evaluation, so every wait that finds
 its flag not yet set gives up at once (no kernel waits out its poll limit and nothing hangs).
-The getter must then report PIMD_ERR_DEVICE, and the next evaluation must be valid again: the
-same forces as before the failure, bit for bit (the schedule's arithmetic is deterministic)."""
+Every synchronising call must then report PIMD_ERR_DEVICE, the run must stay halted (no steps,
+no evaluations, no new trace records) until the state is set again, and the evaluation after
+that must be valid: the same forces as before the failure, bit for bit (the schedule's
+arithmetic is deterministic)."""
 import numpy as np
 import pytest
 
@@ -15,12 +17,12 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("helpers", [3, 8])
-def test_failed_waits_are_reported_and_cleared(helpers):
-    from paper_2404_02628_amd.pimd import Context, PimdError, PIMD_ERR_DEVICE
+def test_failed_waits_are_reported_and_halt_the_run(helpers):
+    from paper_2404_02628_amd.pimd import Context, PimdError, PIMD_ERR_DEVICE, PIMD_ERR_STATE
     s = System(n=400, p=8, dim=2, beta=2.0, xi=1.0, pair_amp=1.0, pair_width=0.5, sigma=1.5, seed=61)
     x = random_positions(s.n, s.p, s.dim, s.sigma, s.seed)
     print(f"wait failure: N={s.n}, one chain + {helpers} helpers", flush=True)
-    ctx = Context([s], precision="fp64", recursion_workgroups=helpers + 1)
+    ctx = Context([s], precision="fp64", recursion_workgroups=helpers + 1, trace_capacity=16)
     try:
         ctx.set_state(0, x)
         ctx.compute_forces()
@@ -32,10 +34,23 @@ def test_failed_waits_are_reported_and_cleared(helpers):
             ctx.forces(0)
         assert e.value.code == PIMD_ERR_DEVICE
         assert "timed out" in str(e.value)
+        # halted: the word stays raised for every synchronising call, and nothing runs
+        for call in (ctx.synchronize, lambda: ctx.trace(0, 16), lambda: ctx.density(0), lambda: ctx.get_state(0)):
+            with pytest.raises(PimdError) as e:
+                call()
+            assert e.value.code == PIMD_ERR_DEVICE
+        for call in (ctx.compute_forces, lambda: ctx.step(3, 1)):
+            with pytest.raises(PimdError) as e:
+                call()
+            assert e.value.code == PIMD_ERR_STATE
+        # setting the state restarts the run
+        ctx.set_state(0, x)
         ctx.compute_forces()
         f = ctx.forces(0)
         assert np.array_equal(f, f_ref)
         en = ctx.energies(0)
         assert np.isfinite(en["e_prim"])
+        ctx.step(4, 2)
+        assert len(ctx.trace(0, 16)) == 2
     finally:
         ctx.close()
