@@ -15,6 +15,7 @@ events on the stream it runs on), and the CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -30,6 +31,11 @@ from paper_2404_02628_amd.workloads import WORKLOADS, initial_state  # noqa: E40
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (published)
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (published)
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E (published)
+
+
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def bench_systems(R):
@@ -144,10 +150,12 @@ def traffic_bytes(kind, precision, R):
     return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
 
-def cpu_baseline(sample_steps=40):
-    """The CPU oracle as it stands (sequential FP64, one thread) on a bounded sample (about 15 s)."""
+def _oracle_worker(args):
+    """One oracle replica of the workload: `steps` MD steps after its initial force evaluation,
+    started together with the other workers (barrier); returns (steps, t_start, t_end)."""
+    r, steps, barrier = args
     import oracle
-    s = WORKLOADS["large_gauss"]
+    s = WORKLOADS["large_gauss"].with_(seed=WORKLOADS["large_gauss"].seed + r)
     par = oracle.OracleParams(n=s.n, p=s.p, dim=s.dim, beta=s.beta, xi=s.xi, pair_amp=s.pair_amp,
                               pair_width=s.pair_width)
     md = oracle.OracleMD(dt=s.dt, nhc_len=4)
@@ -155,26 +163,90 @@ def cpu_baseline(sample_steps=40):
     f, _ = oracle.compute_forces(par, x)
     eta = np.zeros((4,) + x.shape)
     veta = np.zeros_like(eta)
+    if barrier is not None:
+        barrier.wait()
     t0 = time.perf_counter()
-    oracle.step(par, md, x, p, eta, veta, f, sample_steps)
-    dt = time.perf_counter() - t0
-    return {"value": sample_steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample_steps} full MD steps of one N=1600, P=32 replica (sequential FP64 C oracle)"}
+    oracle.step(par, md, x, p, eta, veta, f, steps)
+    return steps, t0, time.perf_counter()
 
 
-def energy_precision_error():
-    """Mixed vs FP64 estimator on the same configuration (the precision-induced error)."""
+_BARRIER = None
+
+
+def _pool_init(barrier):
+    global _BARRIER
+    _BARRIER = barrier
+
+
+def _oracle_worker_in_pool(args):
+    return _oracle_worker(args + (_BARRIER,))
+
+
+def cpu_baseline(single_steps=16, worker_steps=6):
+    """The CPU oracle as it stands (plain sequential FP64 C, one thread per replica) on bounded
+    samples of the workload: one replica on one core, then one independent replica per host core
+    (the replicas of a batch are independent, so this is how the oracle uses a multi-core host).
+    Runs before anything touches the GPU, so that the worker processes can be forked."""
+    import multiprocessing as mp
+    import platform
+    import oracle
+    if not os.path.exists(oracle.lib_path()):
+        oracle.build()
+    steps1, a, b = _oracle_worker((0, single_steps, None))
+    one = steps1 / (b - a)
+    # the host's CPU share: the affinity mask, capped at the 16 cores a one-GPU box grants
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    ctx = mp.get_context("fork")
+    barrier = ctx.Barrier(cores)
+    with ctx.Pool(cores, initializer=_pool_init, initargs=(barrier,)) as pool:
+        res = pool.map(_oracle_worker_in_pool, [(r, worker_steps) for r in range(cores)])
+    t0 = min(r[1] for r in res)
+    t1 = max(r[2] for r in res)
+    agg = sum(r[0] for r in res) / (t1 - t0)
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": agg, "unit": "replica-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} independent N=1600, P=32 replicas (seeds 303+r), {worker_steps} full MD steps "
+                      f"each, one process per core, started together; plain sequential FP64 C oracle",
+            "single_core_steps_per_s": one,
+            "single_core_sample": f"{single_steps} full MD steps of one replica on one core",
+            "cpu_model": model, "host_logical_cpus": os.cpu_count()}
+
+
+def energy_precision_error(R, knobs_mixed, knobs_fp64):
+    """Mixed vs FP64 estimators of the same R replicas at their seeded configurations, each in the
+    launch configuration that is timed (batched symmetric pair kernel in mixed precision): the
+    largest relative difference over the replicas, per estimator."""
     out = {}
-    for prec in ("fp64", "mixed"):
-        ctx, _ = make_ctx(prec, 1)
+    for prec, kn in (("fp64", knobs_fp64), ("mixed", knobs_mixed)):
+        ctx, _ = make_ctx(prec, R, knobs=kn)
         try:
             ctx.compute_forces()
-            out[prec] = ctx.energies(0)
+            out[prec] = [ctx.energies(r) for r in range(R)]
         finally:
             ctx.close()
-    rel = {k: abs(out["mixed"][k] - out["fp64"][k]) / max(abs(out["fp64"][k]), 1e-300)
-           for k in ("e_prim", "e_vir", "u_pair", "v_exch")}
+    rel = {}
+    for k in ("e_prim", "e_vir", "u_pair", "v_exch"):
+        rel[k] = max(abs(m[k] - f[k]) / max(abs(f[k]), 1e-300) for m, f in zip(out["mixed"], out["fp64"]))
     return rel
+
+
+def lse2_latency_ns():
+    """ns of one dependent two-term log-sum-exp (the library's FP64 exp and log, one wavefront),
+    from the committed issue-rate record, or None."""
+    import re
+    path = os.path.join(ROOT, "profiles", "valu_mfma_issue_rates.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"^lse2\s+\S+ ms\s+([0-9.]+) ns", open(path).read(), re.M)
+    return float(m.group(1)) if m else None
 
 
 def main():
@@ -190,6 +262,10 @@ def main():
               "replicas, or the imaginary-time slices of one replica, would shard over GPUs); use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    # the CPU baseline forks its worker processes, so it runs before anything touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    if cpu is not None:
+        progress(f"cpu baseline: {cpu['value']:.2f} replica-steps/s on {cpu['cores']} cores")
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -206,6 +282,13 @@ def main():
     tune64 = autotune.tune(bench_systems(1), "fp64", steps=20, warmup=5)
     t64, _, _ = run_path("fp64", 1, args.steps, args.warmup, knobs=tune64.best)
     fp64_sps = args.steps / t64
+    progress(f"fp64 single replica: {fp64_sps:.1f} steps/s")
+    # its recursion per chain row: both directions run concurrently, each a chain of N rows
+    _, _, times64 = run_path("fp64", 1, max(20, args.steps // 5), args.warmup, profile=True,
+                             knobs=dataclasses.replace(tune64.best, graphs=False))
+    rec_ms, rec_n = times64.get("recursion", (0.0, 0))
+    rec_ns_per_row = rec_ms / max(rec_n, 1) * 1e6 / base.n
+    progress(f"fp64 single replica recursion: {rec_ns_per_row:.1f} ns per chain row")
 
     # mixed batched: choose R by a short sweep unless given
     curve = {}
@@ -216,6 +299,7 @@ def main():
             n = max(20, args.steps // 10)
             t, _, _ = run_path("mixed", r, n, 5)
             curve[r] = r * n / t
+            progress(f"mixed R={r}: {curve[r]:.1f} replica-steps/s")
         # the smallest batch within 2% of the best rate: short sweep runs differ by a few percent
         # from run to run, and a larger batch only costs memory once the device is full
         best = max(curve.values())
@@ -228,9 +312,21 @@ def main():
     best = tunemix.best
     tmix, systems, _ = run_path("mixed", R, args.steps, args.warmup, knobs=best)
     _, _, times = run_path("mixed", R, args.steps, args.warmup, profile=True,
-                           knobs=autotune.Knobs(best.recursion_workgroups, best.pair_kernel, False))
+                           knobs=dataclasses.replace(best, graphs=False))
     sps = R * args.steps / tmix
     beads = sum(s.n * s.p for s in systems)
+    progress(f"mixed R={R} timed: {sps:.1f} replica-steps/s")
+
+    # FP64 at the same batch size: the precision gain apart from the batching gain
+    tune64b = autotune.tune(bench_systems(R), "fp64", steps=5, warmup=2)
+    steps64b = max(20, args.steps // 5)
+    t64b, _, _ = run_path("fp64", R, steps64b, args.warmup, knobs=tune64b.best)
+    fp64_batched_sps = R * steps64b / t64b
+    progress(f"fp64 R={R}: {fp64_batched_sps:.1f} replica-steps/s")
+    mixed_single_sps = curve.get(1)
+    if mixed_single_sps is None:
+        t1, _, _ = run_path("mixed", 1, max(20, args.steps // 10), 5)
+        mixed_single_sps = max(20, args.steps // 10) / t1
 
     # roofline of the dominant kernel of the mixed batched step
     dom = max(times.items(), key=lambda kv: kv[1][0])
@@ -248,8 +344,9 @@ def main():
         kernels[k] = {"avg_us": avg * 1e6, "launches": v[1], "total_ms": v[0], "bound": b,
                       "achieved": ach, "unit": un, "frac": ach / pk}
 
-    rel = energy_precision_error()
-    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    rel = energy_precision_error(R, best, tune64b.best)
+    progress(f"mixed vs fp64 estimators over {R} replicas: {rel}")
+    lse2 = lse2_latency_ns()
     rec = {
         "metric": "PIMD steps/s & bead-updates/s at N=1600,P=32: mixed vs FP64 at <=0.2% energy error",
         "value": sps,
@@ -269,8 +366,17 @@ def main():
         "bead_updates_per_s": sps * beads / R,
         "fp64_single_steps_per_s": fp64_sps,
         "fp64_single_bead_updates_per_s": fp64_sps * base.n * base.p,
+        "fp64_batched_steps_per_s": fp64_batched_sps,
+        "mixed_single_steps_per_s": mixed_single_sps,
         "speedup_mixed_batched_vs_fp64": sps / fp64_sps,
+        "gain_precision_at_R": sps / fp64_batched_sps,
+        "gain_batching_fp64": fp64_batched_sps / fp64_sps,
+        "gain_precision_single": mixed_single_sps / fp64_sps,
         "energy_rel_err_mixed_vs_fp64_same_config": rel,
+        "recursion_fp64_single": {"ns_per_chain_row": rec_ns_per_row, "rows": base.n,
+                                  "schedule_workgroups": tune64.best.recursion_workgroups,
+                                  "lse2_latency_model_ns": lse2,
+                                  "ratio_to_model": (rec_ns_per_row / lse2) if lse2 else None},
         "replica_curve_steps_per_s": curve,
         "autotune": {"mixed": {"best": best.as_kwargs(),
                                "s_per_step": {str(k.as_kwargs()): v for k, v in tunemix.seconds_per_step.items()}},

@@ -16,11 +16,18 @@
 //   copy, copy4, triad   FP64 streams over 512 MiB arrays (y = x; z = x + s y) in two launch
 //            shapes: what a plain kernel gets out of HBM, for comparison with the memory-bound
 //            kernels (springs, integrator)
+//   lse2     latency, not throughput: one wavefront runs X <- -log(a + exp(c - X)) with the
+//            library's FP64 exponential and logarithm, every iteration depending on the last.
+//            This is the least a sequential exchange recursion (Eqs. 6, 11) must spend per row
+//            if everything but the newest term is summed off the chain: the model against
+//            which the recursion kernels' time per row is read.
 // The results decide the pair kernel's design: whether a Gram-matrix formulation on the matrix
 // cores (|r_i - r_j|^2 = |r_i|^2 + |r_j|^2 - 2 r_i.r_j) can beat the plain vector form.
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstdlib>
+
+#include "../csrc/fast_exp.h"
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -178,6 +185,17 @@ static double stream_gbs(L launch, double bytes) {
   return bytes / (best * 1e-3) / 1e9;
 }
 
+// One wavefront: a dependent chain of two-term log-sum-exps (see lse2 above).
+__global__ __launch_bounds__(64) void k_lse2_chain(double* out, int iters) {
+  __shared__ double tab[pimd::kExpTable];
+  tab[threadIdx.x] = pimd::exp_table_entry(threadIdx.x);   // 64 threads fill the 64 entries
+  __syncthreads();
+  double x = 0.1 * threadIdx.x;
+  const double a = 1.0 + 1e-3 * threadIdx.x, c = 0.25;
+  for (int i = 0; i < iters; ++i) x = -pimd::fast_log(a + pimd::fast_exp(c - x, tab));
+  out[threadIdx.x] = x;
+}
+
 template <typename K>
 static double time_ms(K kern, float* out, int iters) {
   hipEvent_t a, b;
@@ -218,6 +236,30 @@ int main() {
   ms = time_ms(k_pair, out, iters);
   std::printf("pair    %8.3f ms  %6.2f cycles per 64 pairs (one wave step)\n", ms, cycles(ms, 8));
   CK(hipFree(out));
+
+  {
+    double* o64 = nullptr;
+    CK(hipMalloc(&o64, 64 * sizeof(double)));
+    const int chain = 200000;
+    hipEvent_t a, b;
+    CK(hipEventCreate(&a));
+    CK(hipEventCreate(&b));
+    hipLaunchKernelGGL(k_lse2_chain, dim3(1), dim3(64), 0, 0, o64, 1000);   // warm-up
+    CK(hipGetLastError());
+    CK(hipDeviceSynchronize());
+    CK(hipEventRecord(a));
+    hipLaunchKernelGGL(k_lse2_chain, dim3(1), dim3(64), 0, 0, o64, chain);
+    CK(hipEventRecord(b));
+    CK(hipEventSynchronize(b));
+    float lms = 0.f;
+    CK(hipEventElapsedTime(&lms, a, b));
+    const double ns = lms * 1e6 / chain;
+    std::printf("lse2    %8.3f ms  %6.1f ns (%5.0f cycles at 2.4 GHz) per dependent two-term log-sum-exp\n",
+                lms, ns, ns * 2.4);
+    CK(hipEventDestroy(a));
+    CK(hipEventDestroy(b));
+    CK(hipFree(o64));
+  }
 
   const long long n = 64LL << 20;   // doubles per array: 512 MiB
   double *x = nullptr, *y = nullptr, *z = nullptr;
