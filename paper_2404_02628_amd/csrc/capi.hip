@@ -60,11 +60,11 @@ struct Plan {
   std::vector<RepDev> reps;
   std::vector<int4> springwork, pairwork, intwork;
   std::vector<int> reporder;  // replica of each recursion workgroup pair, in launch order
-  size_t off[32]{};
+  size_t off[40]{};
   size_t total = 0;
 };
 
-enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LINK, S_EINT, S_GF, S_GB, S_COLREC, S_AVG,
+enum Seg { S_REPS = 0, S_X, S_P, S_F, S_FPAIR, S_XS, S_ETA, S_VETA, S_ENDS, S_LINK, S_EINT, S_GF, S_GB, S_COLREC, S_AVG, S_LAM,
            S_FLAGS, S_PARTIAL, S_ERR,
            S_SPRINGP, S_PAIRP, S_REDP, S_REC, S_TRACE, S_TRACECNT, S_DENS, S_DENSN, S_SPRINGW, S_PAIRW, S_INTW, S_DBG,
            S_REPORD, S_COUNT };
@@ -238,6 +238,7 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
   sz[S_LINK] = sz[S_EINT] = sz[S_GF] = sz[S_GB] = 8ull * NP;
   sz[S_COLREC] = 32ull * 2 * NP;
   sz[S_AVG] = 8ull * 2 * (d.D + 1) * NP;
+  sz[S_LAM] = 8ull * 2 * NP;
   sz[S_FLAGS] = 4ull * 4 * NP;
   sz[S_PARTIAL] = 8ull * 2 * (d.D + 3) * NP;
   sz[S_ERR] = 256;
@@ -262,6 +263,32 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
     o += (size_t)round_up((long long)sz[s], 256);
   }
   pl.total = o;
+}
+
+// Schedule of the exchange recursions: helper workgroups per cooperative chain (0: one workgroup
+// per replica and direction).  Helpers pay when a few replicas would otherwise leave most of the
+// device idle.  `req` is pimd_config.recursion_workgroups.
+int choose_helpers(int req, const Dims& d) {
+  int dev = 0, cus = 0, coop = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+    return 0;
+  const int per_cu = recursion_coop_max_blocks_per_cu(d.D, d.maxn);
+  const long long nchains = 2LL * d.R;
+  const long long capacity = (long long)per_cu * cus;
+  const int max_nblk = (d.maxn + 1 + kTile - 1) / kTile;
+  const long long useful = std::max(0, max_nblk - 2);
+  long long H = 0;
+  if (req > 1) H = req - 1;
+  else if (req == 0 && nchains * 4 <= cus && useful > 0) {
+    // as many as fit, but about one helper per three row blocks: more only add polling
+    // (one replica, FP64: N = 10^4 runs 7% faster with 52 helpers than with 127, while
+    // N = 4 10^4 still gains up to the device's capacity)
+    H = std::min<long long>(capacity / nchains - 1, std::max<long long>(24, max_nblk / 3));
+  }
+  H = std::min(H, useful);
+  if (nchains * (1 + H) > capacity) H = capacity / nchains - 1;
+  return (int)std::max(0LL, H);
 }
 
 }  // namespace
@@ -493,6 +520,7 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   w.gb = (double*)(c->ws + off[S_GB]);
   w.colrec = (double4*)(c->ws + off[S_COLREC]);
   w.avg = (double*)(c->ws + off[S_AVG]);
+  w.lam = (double*)(c->ws + off[S_LAM]);
   w.flags = (int*)(c->ws + off[S_FLAGS]);
   w.partial = (double*)(c->ws + off[S_PARTIAL]);
   w.err = (int*)(c->ws + off[S_ERR]);
@@ -536,32 +564,7 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) return cleanup(fail(PIMD_ERR_DEVICE, std::string("pimd_create: ") + hipGetErrorString(e)));
-  // Schedule of the exchange recursions: cooperative chain + helpers when a few replicas would
-  // otherwise leave most of the device idle.
-  {
-    int dev = 0, cus = 0, coop = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop) {
-      const int per_cu = recursion_coop_max_blocks_per_cu(c->pl.d.D, c->pl.d.maxn);
-      const long long nchains = 2LL * c->pl.d.R;
-      const long long capacity = (long long)per_cu * cus;
-      int max_nblk = 0;
-      for (auto& r : c->pl.reps) max_nblk = std::max(max_nblk, (r.n + 1 + kTile - 1) / kTile);
-      const long long useful = std::max(0, max_nblk - 2);
-      long long H = 0;
-      const int req = cfg->recursion_workgroups;
-      if (req > 1) H = req - 1;
-      else if (req == 0 && nchains * 4 <= cus && useful > 0) {
-        // as many as fit, but about one helper per three row blocks: more only add polling
-        // (one replica, FP64: N = 10^4 runs 7% faster with 52 helpers than with 127, while
-        // N = 4 10^4 still gains up to the device's capacity)
-        H = std::min<long long>(capacity / nchains - 1, std::max<long long>(24, max_nblk / 3));
-      }
-      H = std::min(H, useful);
-      if (nchains * (1 + H) > capacity) H = capacity / nchains - 1;
-      c->helpers = (int)std::max(0LL, H);
-    }
-  }
+  c->helpers = choose_helpers(cfg->recursion_workgroups, c->pl.d);
   *out = c;
   return PIMD_OK;
 }

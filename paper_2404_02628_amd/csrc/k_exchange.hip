@@ -31,9 +31,15 @@
 // (sum_{l'} Pr[l->l'] a_{l'}, and sum Pr close for the energy) are weighted averages over the
 // terms of forward row l, and the column sums of Eq. 15 (sum_l Pr[l->u] b_l) weighted averages
 // over backward row N+1-u.  Each recursion row therefore also accumulates the term-weighted
-// average of its column points q_j and of |p_i - q_j|^2; a per-particle pass applies the row
-// factors, adds Pr[l -> l+1] = -expm1(G^f_l + G^b_{N-l} - G^f_N - beta link_l) (Eq. 13) and forms
-// the end-bead forces of Eqs. 15-16.  The N^2/2 probabilities are never stored or recomputed.
+// average of its column points q_j and of |p_i - q_j|^2 + lam_{i-1} - lam_j, where lam is the
+// prefix of link_l / c: c times that payload is the cycle energy E^{[j+1,i]} minus its internal
+// energies (its closing term plus the links inside it), so the expected spring energy S of the
+// estimators is a sum of non-negative terms, each as accurate as its probability.  A per-particle
+// pass applies the row factors, adds Pr[l -> l+1] = -expm1(G^f_l + G^b_{N-l} - G^f_N - beta
+// link_l) (Eq. 13) and forms the end-bead forces of Eqs. 15-16.  The N^2/2 probabilities are never
+// stored or recomputed.  (Eq. 13 in that form is the difference of potentials of size up to
+// beta sum link, so a small Pr[l -> l+1] carries an absolute error of their rounding; the forces
+// take it at that absolute size, while S never multiplies it by a link energy.)
 //
 // Recursion schedule (one workgroup per replica and direction, four wavefronts).  Rows are
 // processed in blocks of 64 (lane = row).  For a block: (0) a reference R_i = the largest term of
@@ -110,6 +116,7 @@ __device__ inline double xi_term(int k, double lnxi) {
 struct RowCtx {
   int i;
   double rowc, bc, lnxi;
+  double lrow;   // lam_{i-1}: the links of a cycle [j+1, i] are c (lrow - lam_j)
 };
 
 // term t_{i,j} = alpha_{i,j} + G_j and |p_i - q_j|^2 for column record r4 = {q_j, gamma_j + G_j}.
@@ -126,20 +133,24 @@ __device__ inline double term_of(const RowCtx& rc, const double (&pi)[D], const 
 // two interleaved accumulator sets, records prefetched one round ahead.
 template <int D, int XM>
 __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], double R, const double4* __restrict__ rec,
-                                  int ja, int jb, const double* tab, double& s_out, double (&P)[D + 1]) {
+                                  const double* __restrict__ lam, int ja, int jb, const double* tab, double& s_out,
+                                  double (&P)[D + 1]) {
   double s[2] = {0.0, 0.0}, pq[2][D + 1];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int q = 0; q <= D; ++q) pq[h][q] = 0.0;
-  auto ld = [&](double4 (&dst)[4], int j0) {
+  auto ld = [&](double4 (&dst)[4], double (&dl)[4], int j0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) dst[u] = rec[min(j0 + u, jb - 1)];
+    for (int u = 0; u < 4; ++u) {
+      dst[u] = rec[min(j0 + u, jb - 1)];
+      dl[u] = lam[min(j0 + u, jb - 1)];
+    }
   };
   // the reference enters the row constant once instead of every term
-  const RowCtx rr{rc.i, rc.rowc - R, rc.bc, rc.lnxi};
+  const RowCtx rr{rc.i, rc.rowc - R, rc.bc, rc.lnxi, rc.lrow};
   // groups of four columns; only the last group can be partial, and only it masks its terms
-  auto group = [&](const double4 (&g)[4], int j0) {
+  auto group = [&](const double4 (&g)[4], const double (&gl)[4], int j0) {
     const bool full = j0 + 4 <= jb;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -153,18 +164,19 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
       const double qv[3] = {g[u].x, g[u].y, g[u].z};
 #pragma unroll
       for (int c = 0; c < D; ++c) pq[h][c] = fma(e, qv[c], pq[h][c]);
-      pq[h][D] = fma(e, d2, pq[h][D]);
+      pq[h][D] = fma(e, d2 + (rr.lrow - gl[u]), pq[h][D]);
     }
   };
   // two record buffers in turn, each loaded one group ahead (no register copies between groups)
   double4 bufA[4], bufB[4];
-  if (ja < jb) ld(bufA, ja);
+  double lamA[4], lamB[4];
+  if (ja < jb) ld(bufA, lamA, ja);
   for (int j0 = ja; j0 < jb; j0 += 8) {
-    if (j0 + 4 < jb) ld(bufB, j0 + 4);
-    group(bufA, j0);
+    if (j0 + 4 < jb) ld(bufB, lamB, j0 + 4);
+    group(bufA, lamA, j0);
     if (j0 + 4 >= jb) break;
-    if (j0 + 8 < jb) ld(bufA, j0 + 8);
-    group(bufB, j0 + 4);
+    if (j0 + 8 < jb) ld(bufA, lamA, j0 + 8);
+    group(bufB, lamB, j0 + 4);
   }
   s_out = s[0] + s[1];
 #pragma unroll
@@ -174,8 +186,9 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
 // Same sums with a running maximum m (result = exp(m) * (s, P)); used when a term exceeds the
 // fixed reference by more than the double range.
 template <int D, int XM>
-__device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], const double4* __restrict__ rec, int ja,
-                                   int jb, const double* tab, double& m_out, double& s_out, double (&P)[D + 1]) {
+__device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], const double4* __restrict__ rec,
+                                   const double* __restrict__ lam, int ja, int jb, const double* tab, double& m_out,
+                                   double& s_out, double (&P)[D + 1]) {
   double m = -1e300, s = 0.0, pq[D + 1];
 #pragma unroll
   for (int q = 0; q <= D; ++q) pq[q] = 0.0;
@@ -183,6 +196,7 @@ __device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], cons
     const double4 r4 = rec[j];
     double d2;
     const double t = term_of<D, XM>(rc, pi, r4, j, d2);
+    const double v = d2 + (rc.lrow - lam[j]);
     const double dl = t - m;
     const double e = fast_exp(-fabs(dl), tab);
     const double qv[3] = {r4.x, r4.y, r4.z};
@@ -190,13 +204,13 @@ __device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], cons
       s = fma(s, e, 1.0);
 #pragma unroll
       for (int c = 0; c < D; ++c) pq[c] = fma(pq[c], e, qv[c]);
-      pq[D] = fma(pq[D], e, d2);
+      pq[D] = fma(pq[D], e, v);
       m = t;
     } else {
       s += e;
 #pragma unroll
       for (int c = 0; c < D; ++c) pq[c] = fma(e, qv[c], pq[c]);
-      pq[D] = fma(e, d2, pq[D]);
+      pq[D] = fma(e, v, pq[D]);
     }
   }
   m_out = m;
@@ -207,13 +221,14 @@ __device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], cons
 
 template <int D, int XM>
 __device__ inline void bulk_rows(const RowCtx& rc, const double (&pi)[D], double R, const double4* __restrict__ rec,
-                                 int ja, int jb, const double* tab, double& m, double& s, double (&P)[D + 1]) {
-  bulk_fixed<D, XM>(rc, pi, R, rec, ja, jb, tab, s, P);
+                                 const double* __restrict__ lam, int ja, int jb, const double* tab, double& m,
+                                 double& s, double (&P)[D + 1]) {
+  bulk_fixed<D, XM>(rc, pi, R, rec, lam, ja, jb, tab, s, P);
   m = R;
   bool bad = !isfinite(s);
 #pragma unroll
   for (int q = 0; q <= D; ++q) bad = bad || !isfinite(P[q]);
-  if (__any(bad)) bulk_online<D, XM>(rc, pi, rec, ja, jb, tab, m, s, P);
+  if (__any(bad)) bulk_online<D, XM>(rc, pi, rec, lam, ja, jb, tab, m, s, P);
 }
 
 template <int D, int XM>
@@ -419,7 +434,8 @@ struct PipeRows {
 // waves w >= W0 split the 64 columns (W0 = 0: consecutive runs of kCols; otherwise with stride
 // kWaves - W0) and store their sums in qp[w].
 template <int D, int W0, class SH>
-__device__ inline void block_payloads(SH& sh, const double* __restrict__ Am, int curp, const double (&pi)[D]) {
+__device__ inline void block_payloads(SH& sh, const double* __restrict__ Am, int curp, const double (&pi)[D],
+                                      double lrow, const double* __restrict__ lamblk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double Q[D + 1];
 #pragma unroll
@@ -435,7 +451,7 @@ __device__ inline void block_payloads(SH& sh, const double* __restrict__ Am, int
       d2 = fma(t, t, d2);
       Q[c] = fma(coef, qv[c], Q[c]);
     }
-    Q[D] = fma(coef, d2, Q[D]);
+    Q[D] = fma(coef, d2 + (lrow - lamblk[sc]), Q[D]);
   };
   if constexpr (W0 == 0) {   // kCols consecutive columns per wave
 #pragma unroll
@@ -486,7 +502,8 @@ __device__ inline void write_avg_kept(const SH& sh, const PipeRows<D>& pr, int s
 template <int D, bool PIPE, class SH, class Idle, class PrevRows>
 __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int cur, int N, bool valid,
                                    double4* __restrict__ rec, double* __restrict__ G, double* __restrict__ av,
-                                   long long npp, const double (&pi)[D], const double4& col_next, int* publish,
+                                   long long npp, const double (&pi)[D], double lrow, const double* __restrict__ lam,
+                                   const double4& col_next, int* publish,
                                    int epoch, RowCarry<D>& cy, Idle&& idle, const double* __restrict__ Am_prev,
                                    PrevRows&& prev_rows, PipeRows<D>* prow) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -518,9 +535,9 @@ __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int
   } else if (wave == 1) {
     idle();   // work for a wave that would otherwise wait for wave 0
   } else if (PIPE && blk > 0) {
-    double pp[D];
-    prev_rows(pp);   // row data of the previous block (reloaded: nothing is kept in registers)
-    block_payloads<D, 2>(sh, Am_prev, cur ^ 1, pp);
+    double pp[D], plr;
+    prev_rows(pp, plr);   // row data of the previous block (reloaded: nothing is kept in registers)
+    block_payloads<D, 2>(sh, Am_prev, cur ^ 1, pp, plr, lam + (blk - 1) * kTile);
   }
   __syncthreads();
   scaled_coefficients<D>(sh, Am);
@@ -545,7 +562,7 @@ __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int
   if (!PIPE) {
     // (5) weighted payloads of the in-block terms, kCols consecutive columns per wave
     // (normalised by wave 0 when it writes the averages at the start of the next block)
-    block_payloads<D, 0>(sh, Am, cur, pi);
+    block_payloads<D, 0>(sh, Am, cur, pi, lrow, lam + blk * kTile);
   }
 }
 
@@ -591,6 +608,37 @@ struct Prefetch {
   }
 };
 
+// lam_j = (1/c) sum_{m<j} link_m for the columns j = 0..N-1 of the forward recursion (zeros for the
+// backward one, whose averages of this payload are not used), written by the whole workgroup
+// before its first block; lds holds one double per wave.  The fence makes the values visible to
+// the other workgroups of a cooperative launch before any panel is published.
+template <int D>
+__device__ inline void link_prefix(const RecMap<D>& mp, double inv_c, double* __restrict__ lam, double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double carry = 0.0;
+  for (int base = 0; base < mp.N; base += blockDim.x) {
+    const int j = base + (int)threadIdx.x;
+    double v = (mp.dir == 0 && j >= 1 && j < mp.N) ? mp.lk[j - 1] * inv_c : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double t = __shfl_up(v, off, 64);
+      if (lane >= off) v += t;
+    }
+    if (lane == 63) lds[wave] = v;
+    __syncthreads();
+    double pre = carry, tot = carry;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wave) pre += lds[w];
+      tot += lds[w];
+    }
+    if (j < mp.N) lam[j] = pre + v;
+    carry = tot;
+    __syncthreads();
+  }
+  __threadfence();
+  __syncthreads();
+}
+
 // One workgroup per replica and direction (batched replicas fill the machine).  Workgroups 2k
 // and 2k + 1 serve replica order[k]: the plan lists replicas in index order or longest first.
 template <int D>
@@ -599,7 +647,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
                                                            const double* __restrict__ link,
                                                            double* __restrict__ gf, double* __restrict__ gb,
                                                            double4* __restrict__ colrec,
-                                                           double* __restrict__ avg,
+                                                           double* __restrict__ avg, double* __restrict__ lamall,
                                                            const int* __restrict__ order) {
   __shared__ RecShared<D, kBatchWaves> sh;
   const int rep = order[blockIdx.x >> 1], dir = blockIdx.x & 1;
@@ -609,6 +657,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
   double* G = (dir == 0 ? gf : gb) + R.part;
   double4* rec = colrec + 2LL * R.part + (long long)dir * R.npp;
   double* av = avg + 2LL * (D + 1) * R.part + (long long)dir * (D + 1) * R.npp;
+  double* lam = lamall + 2LL * R.part + (long long)dir * R.npp;
   const double bc = R.beta * R.c, lnxi = R.lnxi;
   const int xm = xi_mode(R.xi);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -616,6 +665,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
   const long long npp = R.npp;
 
   if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
+  link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0]);
   Prefetch<D> pf;
   pf.load(mp, 0, wave == 0);
   if (wave == 0) sh.col[0][lane] = make_col<D>(mp, lane, pf.q);
@@ -630,8 +680,9 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
 #pragma unroll
     for (int c = 0; c < D; ++c) pi[c] = pf.p[c];
     const double rho = valid ? mp.row_rho(i, pf.lv) : 0.0;
+    const double lrow = valid ? lam[i - 1] : 0.0;
     if (blk + 1 < nblk) pf.load(mp, blk + 1, wave == 0);
-    const RowCtx rc{i, rho, bc, lnxi};
+    const RowCtx rc{i, rho, bc, lnxi, lrow};
     const int jend = blk * kTile;
     // earlier columns this block's rows may take: [jlo, jend); in the block across the species
     // boundary the rows of the second species take none of them
@@ -674,9 +725,9 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
     if (bulk_ok && jend > jlo) {
       const int per = (jend - jlo + kBatchWaves - 1) / kBatchWaves;
       const int ja = min(jend, jlo + wave * per), jb = min(jend, ja + per);
-      if (xm == kXiOne) bulk_rows<D, kXiOne>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
-      else if (xm == kXiZero) bulk_rows<D, kXiZero>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
-      else bulk_rows<D, kXiGen>(rc, pi, Rref, rec, ja, jb, sh.tab, m, s, P);
+      if (xm == kXiOne) bulk_rows<D, kXiOne>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
+      else if (xm == kXiZero) bulk_rows<D, kXiZero>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
+      else bulk_rows<D, kXiGen>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
     }
     sh.pm[wave][lane] = m;
     sh.ps[wave][lane] = s;
@@ -684,8 +735,8 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
     for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = P[q];
     inblock_alpha<D>(sh, sh.Am, cur, blk, i, pi, rho, valid, bc, lnxi, mp.bnd);
     const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
-    solve_block<D, false>(sh, sh.Am, blk, cur, N, valid, rec, G, av, npp, pi, cn, nullptr, 0, cy, [] {}, sh.Am,
-                          [](double (&)[D]) {}, nullptr);
+    solve_block<D, false>(sh, sh.Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, nullptr, 0, cy, [] {},
+                          sh.Am, [](double (&)[D], double&) {}, nullptr);
   }
   __syncthreads();
   if (wave == 0) write_avg<D>(sh, cy, av, npp);
@@ -728,8 +779,8 @@ __device__ inline bool wait_epoch(const int* flag, int epoch, int* err) {
 // Folds columns [j0, j0 + n) into the running log-sum-exp (m, s, P): one rescale per slice.
 // `recs` points at the record of column j0 (global or LDS).
 template <int D, int XM, int NC>
-__device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const double4* recs, int j0, int n,
-                                  const double* tab, double& m, double& s, double (&P)[D + 1]) {
+__device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const double4* recs, const double* lams,
+                                  int j0, int n, const double* tab, double& m, double& s, double (&P)[D + 1]) {
   double t[NC], d2[NC];
   double4 r[NC];
   double mt = -INFINITY;
@@ -737,6 +788,7 @@ __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const
   for (int u = 0; u < NC; ++u) {
     r[u] = recs[min(u, n - 1)];
     t[u] = term_of<D, XM>(rc, pi, r[u], j0 + u, d2[u]);
+    d2[u] += rc.lrow - lams[min(u, n - 1)];   // payload: closing distance plus the cycle's links
     if (u >= n) t[u] = -INFINITY;
     mt = fmax(mt, t[u]);
   }
@@ -758,11 +810,12 @@ __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const
 }
 
 template <int D, int NC>
-__device__ inline void fold_any(int xm, const RowCtx& rc, const double (&pi)[D], const double4* recs, int j0, int n,
-                                const double* tab, double& m, double& s, double (&P)[D + 1]) {
-  if (xm == kXiOne) slice_fold<D, kXiOne, NC>(rc, pi, recs, j0, n, tab, m, s, P);
-  else if (xm == kXiZero) slice_fold<D, kXiZero, NC>(rc, pi, recs, j0, n, tab, m, s, P);
-  else slice_fold<D, kXiGen, NC>(rc, pi, recs, j0, n, tab, m, s, P);
+__device__ inline void fold_any(int xm, const RowCtx& rc, const double (&pi)[D], const double4* recs,
+                                const double* lams, int j0, int n, const double* tab, double& m, double& s,
+                                double (&P)[D + 1]) {
+  if (xm == kXiOne) slice_fold<D, kXiOne, NC>(rc, pi, recs, lams, j0, n, tab, m, s, P);
+  else if (xm == kXiZero) slice_fold<D, kXiZero, NC>(rc, pi, recs, lams, j0, n, tab, m, s, P);
+  else slice_fold<D, kXiGen, NC>(rc, pi, recs, lams, j0, n, tab, m, s, P);
 }
 
 template <int D, bool PIPE>
@@ -771,7 +824,8 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
                                                                 const double* __restrict__ link,
                                                                 double* __restrict__ gf, double* __restrict__ gb,
                                                                 double4* __restrict__ colrec,
-                                                                double* __restrict__ avg, int* __restrict__ flags,
+                                                                double* __restrict__ avg, double* __restrict__ lamall,
+                                                                int* __restrict__ flags,
                                                                 double* __restrict__ partial, int* __restrict__ err,
                                                                 int nchains, int H) {
   __shared__ RecShared<D, kCoopWaves> sh;
@@ -788,6 +842,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   double* G = (dir == 0 ? gf : gb) + R.part;
   double4* rec = colrec + 2LL * R.part + (long long)dir * R.npp;
   double* av = avg + 2LL * (D + 1) * R.part + (long long)dir * (D + 1) * R.npp;
+  double* lam = lamall + 2LL * R.part + (long long)dir * R.npp;
   int* panel_ready = flags + 4LL * R.part + (long long)(2 * dir) * R.npp;
   int* part_ready = flags + 4LL * R.part + (long long)(2 * dir + 1) * R.npp;
   double* pt = partial + 2LL * (D + 3) * R.part + (long long)dir * (D + 3) * R.npp;  // [D+3][npp]: m, s, P
@@ -799,17 +854,22 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
 
   if (is_chain) {
+    link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0]);   // before panel 0 is published
     Prefetch<D> pf;
     pf.load(mp, 0, wave == 0);
     if (wave == 0) sh.col[0][lane] = make_col<D>(mp, lane, pf.q);
     RowCarry<D> cy{};
     // row data of block b (zero for rows outside 1..N, as the prefetch leaves them)
-    auto rows_of = [&](int b, double (&pp)[D]) {
+    auto rows_of = [&](int b, double (&pp)[D], double& lr) {
       const int ip = b * kTile + lane;
 #pragma unroll
       for (int c = 0; c < D; ++c) pp[c] = 0.0;
       double lv = 0.0;
-      if (ip >= 1 && ip <= N) mp.row_load(ip, pp, lv);
+      lr = 0.0;
+      if (ip >= 1 && ip <= N) {
+        mp.row_load(ip, pp, lv);
+        lr = lam[ip - 1];
+      }
     };
     // wave 1 holds the helper's partial sums over panels 0..blk-2 for the rows of block blk; it
     // fetches them during the previous block, while wave 0 combines and scales
@@ -826,8 +886,9 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
 #pragma unroll
       for (int c = 0; c < D; ++c) pi[c] = pf.p[c];
       const double rho = valid ? mp.row_rho(i, pf.lv) : 0.0;
+      const double lrow = valid ? lam[i - 1] : 0.0;
       if (blk + 1 < nblk) pf.load(mp, blk + 1, wave == 0);
-      const RowCtx rc{i, rho, bc, lnxi};
+      const RowCtx rc{i, rho, bc, lnxi, lrow};
       // coefficient buffers alternate by block: the previous block's stay intact for its payloads
       double* Am = (PIPE && (blk & 1)) ? am_alt : sh.Am;
       const double* Am_prev = (PIPE && !(blk & 1)) ? am_alt : sh.Am;
@@ -842,7 +903,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
       if (blk >= 1 && bulk_ok) {
         const int j0 = (blk - 1) * kTile + wave * kCoopCols, js = max(j0, jlo);
         if (js < j0 + kCoopCols)
-          fold_any<D, kCoopCols>(xm, rc, pi, sh.col[cur ^ 1] + wave * kCoopCols + (js - j0), js,
+          fold_any<D, kCoopCols>(xm, rc, pi, sh.col[cur ^ 1] + wave * kCoopCols + (js - j0), lam + js, js,
                                  j0 + kCoopCols - js, sh.tab, m, s, P);
       }
       if (bulk_ok && have_part && hs > 0.0) {
@@ -875,17 +936,18 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
           }
         }
       };
-      solve_block<D, PIPE>(sh, Am, blk, cur, N, valid, rec, G, av, npp, pi, cn, panel_ready + blk, epoch, cy,
-                           fetch_next, Am_prev, [&](double (&pp)[D]) { rows_of(blk - 1, pp); }, &prow);
+      solve_block<D, PIPE>(sh, Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, panel_ready + blk, epoch,
+                           cy, fetch_next, Am_prev, [&](double (&pp)[D], double& lr) { rows_of(blk - 1, pp, lr); },
+                           &prow);
     }
     // the last block's payloads (pipelined) and row averages
     __syncthreads();
     if (PIPE) {
       const int lastc = (nblk - 1) & 1;
       if (wave >= 2) {
-        double pp[D];
-        rows_of(nblk - 1, pp);
-        block_payloads<D, 2>(sh, lastc ? am_alt : sh.Am, lastc, pp);
+        double pp[D], lr;
+        rows_of(nblk - 1, pp, lr);
+        block_payloads<D, 2>(sh, lastc ? am_alt : sh.Am, lastc, pp, lr, lam + (nblk - 1) * kTile);
       }
       __syncthreads();
       if (wave == 2) write_avg_kept<D, 2>(sh, prow, lastc, nblk - 1, N, av, npp);
@@ -906,7 +968,10 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
     for (int c = 0; c < D; ++c) pi[c] = 0.0;
     if (valid) mp.row_load(i, pi, lv);
     const double rho = valid ? mp.row_rho(i, lv) : 0.0;
-    const RowCtx rc{i, rho, bc, lnxi};
+    // the rows' lam_{i-1} is read once a panel has been acquired: the chain writes lam before it
+    // publishes panel 0, and nothing orders that write before this helper's first wait
+    RowCtx rc{i, rho, bc, lnxi, 0.0};
+    bool have_lrow = false;
     const int jlo = blk * kTile > mp.bnd ? mp.bnd : 0;
     const bool bulk_ok = valid && (i <= mp.bnd || jlo == mp.bnd);
     double m = -1e300, s = 0.0, P[D + 1];
@@ -929,9 +994,13 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
         __syncthreads();
         if (ready < 0) return;   // a wait failed: the error word is raised, stop this helper
       }
+      if (!have_lrow) {
+        rc.lrow = valid ? lam[i - 1] : 0.0;
+        have_lrow = true;
+      }
       const int j0 = c * kTile + wave * kCoopCols, js = max(j0, jlo);
       if (bulk_ok && js < j0 + kCoopCols)
-        fold_any<D, kCoopCols>(xm, rc, pi, rec + js, js, j0 + kCoopCols - js, sh.tab, m, s, P);
+        fold_any<D, kCoopCols>(xm, rc, pi, rec + js, lam + js, js, j0 + kCoopCols - js, sh.tab, m, s, P);
     }
     sh.pm[wave][lane] = m;
     sh.ps[wave][lane] = s;
@@ -965,7 +1034,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s) {
   dim3 grid((unsigned)(2 * d.R)), block(64 * kBatchWaves);
 #define L(DD) hipLaunchKernelGGL(k_recursion<DD>, grid, block, 0, s, w.reps, w.ends, w.link, w.gf, w.gb, w.colrec, w.avg, \
-                              w.reporder)
+                              w.lam, w.reporder)
   switch (d.D) {
     case 1: L(1); break;
     case 2: L(2); break;
@@ -994,11 +1063,12 @@ static hipError_t launch_coop_d(const Dims& d, const DevPtrs& w, int H, hipStrea
   double* gb = w.gb;
   double4* colrec = w.colrec;
   double* avg = w.avg;
+  double* lamall = w.lam;
   int* flags = w.flags;
   double* partial = w.partial;
   int* err = w.err;
   void* args[] = {(void*)&reps, (void*)&ends, (void*)&link, (void*)&gf, (void*)&gb, (void*)&colrec, (void*)&avg,
-                  (void*)&flags, (void*)&partial, (void*)&err, (void*)&nchains, (void*)&H};
+                  (void*)&lamall, (void*)&flags, (void*)&partial, (void*)&err, (void*)&nchains, (void*)&H};
   return hipLaunchCooperativeKernel((const void*)k_recursion_coop<D, PIPE>, grid, block, args, 0, s);
 }
 
@@ -1060,11 +1130,14 @@ __device__ inline double prob_next(int l, int N, int na, const double* lk, const
 //   sum_{l'<=L} Pr[L -> l'] = exp(G^f_L + G^b_{N-L} - G^f_N - beta link_L) =: w_end   (forward row L)
 //   sum_{l>=L} Pr[l -> L]  = exp(G^b_{N+1-L} + G^f_{L-1} - G^f_N - beta link_{L-1}) =: w_start
 //                                                                          (backward row N+1-L)
-// and the weighted averages of the forward row (a_{l'}, |b_L - a_{l'}|^2) and of the backward
-// row (b_l).  With the Pr[L -> L+1] and Pr[L-1 -> L] terms of Eq. 13 added, Eqs. 15-16 give
+// and the weighted averages of the forward row (a_{l'}, |b_L - a_{l'}|^2 + lam_{L-1} - lam_{l'-1})
+// and of the backward row (b_l).  With the Pr[L -> L+1] and Pr[L-1 -> L] terms of Eq. 13 added,
+// Eqs. 15-16 give
 //   F(bead P of L) += -kappa (rowsum (2 b_L - r_L^{P-1}) - sum_{l'} Pr[L->l'] a_{l'})
 //   F(bead 1 of L) += -kappa (colsum (2 a_L - r_L^2)     - sum_{l}  Pr[l->L] b_l)
-// and the expected spring energy gets w_end c avg|b_L - a_{l'}|^2 + Pr[L -> L+1] link_L.
+// and the expected spring energy S = sum_{l'<=L} Pr[L -> l'] E^{[l',L]} gets, beyond the internal
+// energies, w_end c avg(|b_L - a_{l'}|^2 + lam_{L-1} - lam_{l'-1}): the closing terms and the links
+// of every cycle that ends at L.
 template <int D>
 __global__ __launch_bounds__(256) void k_probs_reduce(const RepDev* __restrict__ reps, const int4* __restrict__ work,
                                                       const double* __restrict__ x, double* __restrict__ f,
@@ -1107,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_probs_reduce(const RepDev* __restrict__
       fr[((long long)c * P + (P - 1)) * N + l] += -kap * (rs * (2.0 * bl - rP1) - ra);
       fr[((long long)c * P + 0) * N + l] += -kap * (cs * (2.0 * al - r2) - cb);
     }
-    acc[0] = w_end * R.c * avf[(long long)D * npp + (l + 1)] + pn * lk[l];
+    acc[0] = w_end * R.c * avf[(long long)D * npp + (l + 1)];
     acc[1] = 0.0;
   }
   block_sum<2>(acc, lds);

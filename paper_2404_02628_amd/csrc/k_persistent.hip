@@ -15,7 +15,9 @@
 //     complete: lane i keeps a running log-sum-exp (m_i, s_i) and the weighted sums of its
 //     column points, and G_j = m_j + log s_j is only formed at the end, the term of column j
 //     entering row i as exp(alpha_{i,j} + m_j - m_i) s_j);
-//   * per particle: the probabilities and end-bead forces of Eqs. 12-16 from the row sums.
+//   * per particle: the probabilities and end-bead forces of Eqs. 12-16 from the row sums, and the
+//     expected spring energy from the averaged cycle energies (closing term plus the links inside
+//     the cycle: lam is the prefix of link / c, as in the exchange kernels).
 // Sampled steps add the estimators (trace record) and the density histogram.  At the end the
 // state and the last evaluation's end beads, links, internal energies and potentials go back to
 // the workspace, so every getter of the library sees what the multi-kernel path would leave.
@@ -37,7 +39,7 @@ struct PersistShared {
   double a[D][kPMaxN], b[D][kPMaxN];       // first and last beads
   double lk[kPMaxN], ei[kPMaxN];           // links (0 at the end of a species), E_int
   double g[2][kPMaxN + 1];                 // G^f, G^b, rows 0..N
-  double av[2][D + 1][kPMaxN + 1];         // row averages of q_j and |p_i - q_j|^2
+  double av[2][D + 1][kPMaxN + 1];         // row averages of q_j and |p_i - q_j|^2 + lam_{i-1} - lam_j
   double fe[2][D][kPMaxN];                 // end-bead exchange forces: bead 1, bead P
   double part[kPMaxN][4];                  // per-particle trap, S and pair partial sums
   double red[8 * kPMaxWaves];
@@ -143,6 +145,14 @@ __device__ double persist_evaluate(PersistShared<D>& sh, const RepDev& R, int P,
         rho = i < N ? R.beta * sh.lk[N - i - 1] : 0.0;
       }
     }
+    // lam of column `lane` (forward: prefix of link / c; backward: zero); row i = lane + 1 takes
+    // lam_{i-1} = its own lane's value
+    double lrow = (dir == 0 && lane >= 1 && lane < N) ? sh.lk[lane - 1] / R.c : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double tl = __shfl_up(lrow, off, 64);
+      if (lane >= off) lrow += tl;
+    }
     double m = -INFINITY, s = 0.0, Pq[D + 1];
 #pragma unroll
     for (int q = 0; q <= D; ++q) Pq[q] = 0.0;
@@ -162,6 +172,7 @@ __device__ double persist_evaluate(PersistShared<D>& sh, const RepDev& R, int P,
         for (int c = 0; c < D; ++c) q[c] = sh.b[c][N - j - 1];
         gam = -log((double)(j < bnd ? bnd - j : N - j));
       }
+      const double lamj = read_lane(lrow, j);
       if (lane >= j && i <= N && (i <= bnd || j >= bnd)) {
         double d2 = 0.0;
 #pragma unroll
@@ -170,18 +181,19 @@ __device__ double persist_evaluate(PersistShared<D>& sh, const RepDev& R, int P,
         if (cterm > -INFINITY) {
           const double dl = cterm - m;
           const double ex = fast_exp(-fabs(dl), sh.tab);
+          const double pv = d2 + (lrow - lamj);
           if (dl > 0.0) {
             s = fma(s, ex, sj);
 #pragma unroll
             for (int c = 0; c < D; ++c) Pq[c] = fma(Pq[c], ex, sj * q[c]);
-            Pq[D] = fma(Pq[D], ex, sj * d2);
+            Pq[D] = fma(Pq[D], ex, sj * pv);
             m = cterm;
           } else {
             const double w = ex * sj;
             s += w;
 #pragma unroll
             for (int c = 0; c < D; ++c) Pq[c] = fma(w, q[c], Pq[c]);
-            Pq[D] = fma(w, d2, Pq[D]);
+            Pq[D] = fma(w, pv, Pq[D]);
           }
         }
       }
@@ -217,7 +229,7 @@ __device__ double persist_evaluate(PersistShared<D>& sh, const RepDev& R, int P,
       sh.fe[1][c][l] = -R.kappa * (rs * (2.0 * sh.b[c][l] - rP1) - ra);
       sh.fe[0][c][l] = -R.kappa * (cs * (2.0 * sh.a[c][l] - r2) - cb);
     }
-    sh.part[l][1] = w_end * R.c * sh.av[0][D][l + 1] + pn * sh.lk[l];
+    sh.part[l][1] = w_end * R.c * sh.av[0][D][l + 1];
   }
   __syncthreads();
   if (own) {

@@ -61,6 +61,8 @@ struct DevPtrs {
   double* gf; double* gb;      // [npp]: forward / backward normalised log-potentials, rows 0..N
   double4* colrec;             // [2][npp] per replica: recursion column records {q_j, colc_j + G_j}
   double* avg;                 // [2][dim+1][npp] per replica: weighted row averages of the recursions
+  double* lam;                 // [2][npp] per replica: link prefixes lam_j = (1/c) sum_{m<j} link_m of the
+                               // forward recursion's columns (zeros for the backward one)
   int* flags;                  // [4][npp] per replica: panel / partial ready flags (epochs), per direction
   double* partial;             // [2][dim+3][npp] per replica: helper partial sums (m, s, payloads)
   int* err;                    // status words: [0] raised by a timed-out wait of the cooperative
