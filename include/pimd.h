@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define PIMD_ABI_VERSION 5
+#define PIMD_ABI_VERSION 6
 
 typedef enum {
     PIMD_OK = 0,
@@ -216,6 +216,31 @@ pimd_status pimd_get_state(pimd_ctx* ctx, int32_t r, double* x, double* p, doubl
  * backward exchange potentials (Eqs. 6, 11), connection probabilities (Eqs.
  * 12-14), exchange forces (Eqs. 15-17) and all estimators.  Enqueued only. */
 pimd_status pimd_compute_forces(pimd_ctx* ctx);
+
+/* Bytes of the device scratch that pimd_compute_forces_noalloc holds per GPU. */
+#define PIMD_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the evaluation of pimd_compute_forces for ONE replica
+ * (cfg->n_replicas must be 1), with no context, no workspace and no allocation of any kind.
+ *   x    device array, layout [dim][P][N]: the positions (read only);
+ *   f    device array, layout [dim][P][N]: receives the total force -grad(V_xi + U/P);
+ *   est  device pointer to one pimd_estimates, or NULL: receives the estimators of this
+ *        evaluation (kinetic and nhc_energy are 0, h_conserved is V_xi + U/P, step is 0); all
+ *        NaN if the device found a non-finite force or a cooperative wait gave up;
+ *   hip_stream  hipStream_t (or NULL): every kernel is enqueued on it, nothing synchronises.
+ * Everything else lives in a static device array of PIMD_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends (32 MiB: every single-replica workload up
+ * to N = 4*10^4 at P = 16, d = 3 fits).  All calls on one GPU share it and it keeps the last
+ * call's contents (the call clears what must start at zero): calls that overlap on one GPU race,
+ * so serialise them (one stream, or the caller's own ordering).  pimd_config fields that concern
+ * dynamics or sampling (nhc_len, sy_order, density, trace) are validated and otherwise ignored;
+ * flags and recursion_workgroups choose kernels as for pimd_create.  Errors (returned before
+ * anything is enqueued): PIMD_ERR_INVALID (bad cfg, n_replicas != 1, NULL x or f),
+ * PIMD_ERR_WORKSPACE (the replica needs more scratch than PIMD_NOALLOC_SCRATCH_BYTES; use
+ * pimd_create), PIMD_ERR_DEVICE (HIP launch failure). */
+pimd_status pimd_compute_forces_noalloc(const pimd_config* cfg, const double* x, double* f,
+                                        pimd_estimates* est, void* hip_stream);
 
 /* Total force -grad(V_xi + U/P) of replica r from the last evaluation, layout
  * [dim][P][N].  Synchronises.  Errors: PIMD_ERR_STATE if never evaluated. */

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -265,6 +266,43 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
   pl.total = o;
 }
 
+// Device pointers of the workspace segments laid out by make_plan, from the workspace base.
+void carve(char* ws, const size_t* off, DevPtrs& w) {
+  w.reps = (RepDev*)(ws + off[S_REPS]);
+  w.x = (double*)(ws + off[S_X]);
+  w.p = (double*)(ws + off[S_P]);
+  w.f = (double*)(ws + off[S_F]);
+  w.fpair = (double*)(ws + off[S_FPAIR]);
+  w.xs = (float*)(ws + off[S_XS]);
+  w.eta = (double*)(ws + off[S_ETA]);
+  w.veta = (double*)(ws + off[S_VETA]);
+  w.ends = (double*)(ws + off[S_ENDS]);
+  w.link = (double*)(ws + off[S_LINK]);
+  w.eint = (double*)(ws + off[S_EINT]);
+  w.gf = (double*)(ws + off[S_GF]);
+  w.gb = (double*)(ws + off[S_GB]);
+  w.colrec = (double4*)(ws + off[S_COLREC]);
+  w.avg = (double*)(ws + off[S_AVG]);
+  w.lam = (double*)(ws + off[S_LAM]);
+  w.flags = (int*)(ws + off[S_FLAGS]);
+  w.partial = (double*)(ws + off[S_PARTIAL]);
+  w.err = (int*)(ws + off[S_ERR]);
+  w.springpart = (double*)(ws + off[S_SPRINGP]);
+  w.pairpart = (double*)(ws + off[S_PAIRP]);
+  w.reducepart = (double*)(ws + off[S_REDP]);
+  w.rec = (double*)(ws + off[S_REC]);
+  w.trace = (double*)(ws + off[S_TRACE]);
+  w.tracecount = (long long*)(ws + off[S_TRACECNT]);
+  w.dens = (unsigned long long*)(ws + off[S_DENS]);
+  w.denssamples = (long long*)(ws + off[S_DENSN]);
+  w.springwork = (int4*)(ws + off[S_SPRINGW]);
+  w.pairwork = (int4*)(ws + off[S_PAIRW]);
+  w.reducework = w.springwork;
+  w.intwork = (int4*)(ws + off[S_INTW]);
+  w.dbg = (double*)(ws + off[S_DBG]);
+  w.reporder = (int*)(ws + off[S_REPORD]);
+}
+
 // Schedule of the exchange recursions: helper workgroups per cooperative chain (0: one workgroup
 // per replica and direction).  Helpers pay when a few replicas would otherwise leave most of the
 // device idle.  `req` is pimd_config.recursion_workgroups.
@@ -473,6 +511,83 @@ static pimd_status check_not_halted(pimd_ctx* c) {
   return PIMD_OK;
 }
 
+
+// ------------------------------------------------------------------ no-allocation entry point
+//
+// pimd_compute_forces_noalloc keeps everything an evaluation of one replica needs beyond the
+// caller's positions and forces (per-replica constants, work lists, end beads, links, potentials,
+// recursion records, row averages, partial sums, FP32 shadow, pair forces, estimator record and
+// status words) in `scratch`, a static device array: every GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes the array's name to a kernel (on the host
+// it only stands in for the symbol): its device address on each GPU is looked up once, with that
+// GPU current, and that address is what the kernels receive.
+
+static __device__ __align__(256) unsigned char scratch[PIMD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current GPU (looked up on the first call on that GPU).
+pimd_status noalloc_scratch(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(PIMD_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) return fail(PIMD_ERR_DEVICE, "no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PIMD_OK;
+}
+
+// The per-replica constants and the work lists of a one-replica plan, whose entries follow from
+// their counts (the lists make_plan builds on the host for pimd_create), and the status words
+// lowered.  The cooperative recursion's progress flags are cleared as well: the scratch keeps
+// whatever the previous call left there, and a call of another size lays its arrays out
+// differently, so a stale word could otherwise equal this evaluation's stamp.
+__global__ void k_noalloc_prepare(RepDev rep0, DevPtrs w, long long nspring, long long npair, long long per_slice,
+                                  int ipw, long long nint, long long nflags) {
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (t0 == 0) {
+    *w.reps = rep0;
+    w.reporder[0] = 0;
+    w.err[0] = 0;
+    w.err[2] = 0;
+  }
+  for (long long k = t0; k < nspring; k += stride) w.springwork[k] = make_int4(0, (int)(k * kSpringBlock), 0, 0);
+  for (long long k = t0; k < npair; k += stride)
+    w.pairwork[k] = make_int4(0, (int)(k / per_slice), (int)(k % per_slice) * ipw, 0);
+  for (long long k = t0; k < nint; k += stride) w.intwork[k] = make_int4(0, (int)(k * kIntBlock), 0, 0);
+  for (long long k = t0; k < nflags; k += stride) w.flags[k] = 0;
+}
+
+// The estimator record as pimd_estimates (NaN everywhere if a status word was raised).
+__global__ void k_noalloc_estimates(const double* rec, const int* err, pimd_estimates* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const bool bad = status_halted(err);
+  const double nan = __builtin_nan("");
+  out->v_exch = bad ? nan : rec[kVExch];
+  out->u_trap = bad ? nan : rec[kUTrap];
+  out->u_pair = bad ? nan : rec[kUPair];
+  out->spring_expect = bad ? nan : rec[kSpring];
+  out->virial = bad ? nan : rec[kVirial];
+  out->e_prim = bad ? nan : rec[kEPrim];
+  out->e_vir = bad ? nan : rec[kEVir];
+  out->kinetic = 0.0;
+  out->nhc_energy = 0.0;
+  out->h_conserved = bad ? nan : rec[kHCons];
+  out->step = 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 int pimd_abi_version(void) { return PIMD_ABI_VERSION; }
@@ -503,41 +618,8 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   }
   c->ws = (char*)d_workspace;
   c->s = (hipStream_t)hip_stream;
-  const size_t* off = c->pl.off;
+  carve(c->ws, c->pl.off, c->w);
   DevPtrs& w = c->w;
-  w.reps = (RepDev*)(c->ws + off[S_REPS]);
-  w.x = (double*)(c->ws + off[S_X]);
-  w.p = (double*)(c->ws + off[S_P]);
-  w.f = (double*)(c->ws + off[S_F]);
-  w.fpair = (double*)(c->ws + off[S_FPAIR]);
-  w.xs = (float*)(c->ws + off[S_XS]);
-  w.eta = (double*)(c->ws + off[S_ETA]);
-  w.veta = (double*)(c->ws + off[S_VETA]);
-  w.ends = (double*)(c->ws + off[S_ENDS]);
-  w.link = (double*)(c->ws + off[S_LINK]);
-  w.eint = (double*)(c->ws + off[S_EINT]);
-  w.gf = (double*)(c->ws + off[S_GF]);
-  w.gb = (double*)(c->ws + off[S_GB]);
-  w.colrec = (double4*)(c->ws + off[S_COLREC]);
-  w.avg = (double*)(c->ws + off[S_AVG]);
-  w.lam = (double*)(c->ws + off[S_LAM]);
-  w.flags = (int*)(c->ws + off[S_FLAGS]);
-  w.partial = (double*)(c->ws + off[S_PARTIAL]);
-  w.err = (int*)(c->ws + off[S_ERR]);
-  w.springpart = (double*)(c->ws + off[S_SPRINGP]);
-  w.pairpart = (double*)(c->ws + off[S_PAIRP]);
-  w.reducepart = (double*)(c->ws + off[S_REDP]);
-  w.rec = (double*)(c->ws + off[S_REC]);
-  w.trace = (double*)(c->ws + off[S_TRACE]);
-  w.tracecount = (long long*)(c->ws + off[S_TRACECNT]);
-  w.dens = (unsigned long long*)(c->ws + off[S_DENS]);
-  w.denssamples = (long long*)(c->ws + off[S_DENSN]);
-  w.springwork = (int4*)(c->ws + off[S_SPRINGW]);
-  w.pairwork = (int4*)(c->ws + off[S_PAIRW]);
-  w.reducework = w.springwork;
-  w.intwork = (int4*)(c->ws + off[S_INTW]);
-  w.dbg = (double*)(c->ws + off[S_DBG]);
-  w.reporder = (int*)(c->ws + off[S_REPORD]);
   for (auto& r : c->pl.reps) c->has_pair = c->has_pair || r.amp > 0;
   c->graph_state = (cfg->flags & PIMD_FLAG_GRAPH) ? 0 : 2;
   auto cleanup = [&](pimd_status s2) {
@@ -628,6 +710,54 @@ pimd_status pimd_get_state(pimd_ctx* c, int32_t r, double* x, double* p, double*
     }
   HIPCHK(hipStreamSynchronize(c->s));
   return check_status(c);
+}
+
+pimd_status pimd_compute_forces_noalloc(const pimd_config* cfg, const double* x, double* f, pimd_estimates* est,
+                                        void* hip_stream) {
+  pimd_status st = validate(cfg);
+  if (st != PIMD_OK) return st;
+  if (cfg->n_replicas != 1) return fail(PIMD_ERR_INVALID, "pimd_compute_forces_noalloc evaluates one replica (n_replicas = 1)");
+  if (!x || !f) return fail(PIMD_ERR_INVALID, "x and f must be device arrays");
+  Plan pl;   // the plan without lists stores nothing on the heap
+  make_plan(cfg, pl, false);
+  if (pl.total > (size_t)PIMD_NOALLOC_SCRATCH_BYTES)
+    return fail(PIMD_ERR_WORKSPACE, "this replica needs " + std::to_string(pl.total) +
+                                        " bytes of scratch; pimd_compute_forces_noalloc holds " +
+                                        std::to_string((size_t)PIMD_NOALLOC_SCRATCH_BYTES));
+  void* base = nullptr;
+  if ((st = noalloc_scratch(&base)) != PIMD_OK) return st;
+  DevPtrs w{};
+  carve((char*)base, pl.off, w);
+  // the caller's arrays; no momenta, thermostats, trace, density or debug output
+  w.x = const_cast<double*>(x);
+  w.f = f;
+  w.p = nullptr; w.eta = nullptr; w.veta = nullptr; w.trace = nullptr; w.tracecount = nullptr;
+  w.dens = nullptr; w.denssamples = nullptr; w.dbg = nullptr;
+  Dims d = pl.d;
+  d.M = 0;
+  d.cap = 0;
+  const RepDev& R = pl.rep0;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int helpers = choose_helpers(cfg->recursion_workgroups, d);
+  const long long per_slice = pl.ipw >= (1 << 30) ? 1 : (R.n + pl.ipw - 1) / pl.ipw;
+  const long long nflags = 4LL * d.NPtot;
+  const long long most = std::max({d.nspringwg, d.npairwork, d.nintwg, nflags});
+  const unsigned grid = (unsigned)std::min<long long>(1024, std::max<long long>(1, (most + 255) / 256));
+  hipLaunchKernelGGL(k_noalloc_prepare, dim3(grid), dim3(256), 0, s, R, w, d.nspringwg, d.npairwork, per_slice, pl.ipw,
+                     d.nintwg, nflags);
+  HIPCHK(hipGetLastError());
+  // the evaluation of pimd_compute_forces, every kernel on the caller's stream
+  HIPCHK(launch_springs(d, w, s));
+  HIPCHK(helpers > 0 ? launch_recursion_coop(d, w, helpers, s) : launch_recursion(d, w, s));
+  HIPCHK(launch_probs_reduce(d, w, s));
+  HIPCHK(launch_pair(d, w, est != nullptr, pl.jsplit, s));
+  HIPCHK(launch_integrate_second(d, w, false, s));   // f += pair forces; non-finite check
+  if (est != nullptr) {
+    HIPCHK(launch_estimators(d, w, 0, false, s));
+    hipLaunchKernelGGL(k_noalloc_estimates, dim3(1), dim3(64), 0, s, w.rec, w.err, est);
+    HIPCHK(hipGetLastError());
+  }
+  return PIMD_OK;
 }
 
 pimd_status pimd_compute_forces(pimd_ctx* c) {

@@ -114,7 +114,8 @@ __global__ __launch_bounds__(256) void k_estimators(const RepDev* __restrict__ r
   const RepDev& R = reps[r];
   double acc[2] = {0.0, 0.0};
   const double kT = 1.0 / R.beta;
-  for (long long li = threadIdx.x; li < R.ndof; li += blockDim.x) {
+  // p is NULL for an evaluation without momenta (the kinetic and thermostat terms are then 0)
+  for (long long li = threadIdx.x; p != nullptr && li < R.ndof; li += blockDim.x) {
     const long long gi = R.dof + li;
     const double pv = p[gi];
     acc[0] += 0.5 * pv * pv / R.mp;

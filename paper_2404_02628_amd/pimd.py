@@ -36,6 +36,7 @@ EXPORTED = [
     "pimd_energies", "pimd_trace", "pimd_density", "pimd_reset_accumulators", "pimd_debug_potentials",
     "pimd_debug_probs", "pimd_profile", "pimd_kernel_times", "pimd_kernel_name", "pimd_synchronize",
     "pimd_graph_info", "pimd_cycle_energies", "pimd_init_system", "pimd_debug_fail_waits",
+    "pimd_compute_forces_noalloc",
 ]
 
 
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
         "pimd_cycle_energies": (C.c_int, [_vp, C.c_int32, _dp, _dp]),
         "pimd_init_system": (C.c_int, [_vp, _dp, C.POINTER(C.c_uint64)]),
         "pimd_debug_fail_waits": (C.c_int, [_vp]),
+        "pimd_compute_forces_noalloc": (C.c_int, [C.POINTER(pimd_config), _vp, _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -169,6 +171,11 @@ def pimd_get_state(h, r: int, x=None, p=None, nhc=None, where: int = PIMD_HOST):
 
 def pimd_compute_forces(h):
     _chk(load().pimd_compute_forces(h), "pimd_compute_forces")
+
+
+def pimd_compute_forces_noalloc(cfg: pimd_config, d_x: int, d_f: int, d_est: Optional[int], stream: int):
+    """Device pointers in, nothing allocated: one replica's forces (and estimators, d_est may be None)."""
+    _chk(load().pimd_compute_forces_noalloc(C.byref(cfg), d_x, d_f, d_est, stream), "pimd_compute_forces_noalloc")
 
 
 def pimd_get_forces(h, r: int, f, where: int = PIMD_HOST):

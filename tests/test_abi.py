@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(lib):
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
     assert set(names) == set(lib.EXPORTED)
-    assert lib.pimd_abi_version() == 5
+    assert lib.pimd_abi_version() == 6
 
 
 def _cfg(lib, **over):
@@ -87,3 +87,22 @@ def test_packing_and_split_flags_are_accepted(lib, flags):
     cfg, _keep = _cfg(lib, flags=flags)
     assert lib.pimd_workspace_bytes(cfg) > 0
 
+
+
+def test_noalloc_entry_point_rejects_bad_calls_on_the_host(lib):
+    """pimd_compute_forces_noalloc checks its arguments and the scratch size before any HIP call."""
+    one = (lib.pimd_replica * 1)(lib.pimd_replica(100, 0, 3.0, 1.0, 1.0, 1.0, 1.0, 2.0, 0.5, 0.01, 0.0, 0.0))
+    cfg = lib.pimd_config(1, 12, 2, 1, 4, 3, 50, 0, 0, 0, 5.0, one)
+    raw = C.CDLL(lib.LIB_PATH)
+    raw.pimd_compute_forces_noalloc.restype = C.c_int
+    raw.pimd_compute_forces_noalloc.argtypes = [C.POINTER(lib.pimd_config), C.c_void_p, C.c_void_p, C.c_void_p,
+                                                C.c_void_p]
+    assert raw.pimd_compute_forces_noalloc(C.byref(cfg), None, 256, None, None) == lib.PIMD_ERR_INVALID
+    assert raw.pimd_compute_forces_noalloc(C.byref(cfg), 256, None, None, None) == lib.PIMD_ERR_INVALID
+    two = (lib.pimd_replica * 2)(one[0], one[0])
+    cfg2 = lib.pimd_config(2, 12, 2, 1, 4, 3, 50, 0, 0, 0, 5.0, two)
+    assert raw.pimd_compute_forces_noalloc(C.byref(cfg2), 256, 256, None, None) == lib.PIMD_ERR_INVALID
+    big = (lib.pimd_replica * 1)(lib.pimd_replica(60000, 0, 2.0, 1.0, 1.0, 1.0, 1.0, 0.0, 1.0, 0.01, 0.0, 0.0))
+    cfg3 = lib.pimd_config(1, 16, 3, 0, 4, 3, 50, 0, 0, 0, 5.0, big)
+    assert raw.pimd_compute_forces_noalloc(C.byref(cfg3), 256, 256, None, None) == lib.PIMD_ERR_WORKSPACE
+    assert "bytes of scratch" in lib.pimd_last_error()
