@@ -414,8 +414,8 @@ pimd_status evaluate(pimd_ctx* c, bool est, hipStream_t ms) {
   RUN(K_SPRINGS, ms, launch_springs(d, w, ms));
   const bool fork = c->has_pair;
   if (fork) HIPCHK(hipEventRecord(c->ev_fork, ms));
-  if (c->helpers > 0) RUN(K_RECURSION, ms, launch_recursion_coop(d, w, c->helpers, ms));
-  else RUN(K_RECURSION, ms, launch_recursion(d, w, ms));
+  if (c->helpers > 0) RUN(K_RECURSION, ms, launch_recursion_coop(d, w, c->helpers, est, ms));
+  else RUN(K_RECURSION, ms, launch_recursion(d, w, est, ms));
   RUN(K_REDUCE, ms, launch_probs_reduce(d, w, ms));
   if (c->has_pair) {
     hipStream_t ps = fork ? c->s2 : ms;
@@ -748,7 +748,8 @@ pimd_status pimd_compute_forces_noalloc(const pimd_config* cfg, const double* x,
   HIPCHK(hipGetLastError());
   // the evaluation of pimd_compute_forces, every kernel on the caller's stream
   HIPCHK(launch_springs(d, w, s));
-  HIPCHK(helpers > 0 ? launch_recursion_coop(d, w, helpers, s) : launch_recursion(d, w, s));
+  const bool want_est = est != nullptr;
+  HIPCHK(helpers > 0 ? launch_recursion_coop(d, w, helpers, want_est, s) : launch_recursion(d, w, want_est, s));
   HIPCHK(launch_probs_reduce(d, w, s));
   HIPCHK(launch_pair(d, w, est != nullptr, pl.jsplit, s));
   HIPCHK(launch_integrate_second(d, w, false, s));   // f += pair forces; non-finite check

@@ -23,11 +23,14 @@ constexpr int kExpTable = 64;
 // Fills tab[0..63] with 2^(j/64); call from one workgroup before __syncthreads().
 __host__ __device__ inline double exp_table_entry(int j) { return exp2((double)j / 64.0); }
 
-__host__ __device__ inline double fast_exp(double x, const double* tab) {
+// Without the NaN pass-through (one compare and two selects fewer), for the exchange sums: a NaN
+// argument gives a finite weight there, but the NaN that caused it (a coordinate) also enters the
+// weighted payload sums, which take it on.
+__host__ __device__ inline double fast_exp_finite(double x, const double* tab) {
   const double kInvL = 92.33248261689366;          // 64 / ln 2
   const double kL1 = 0x1.62e42fee00000p-7;         // high 32 bits of ln2 / 64
   const double kL2 = 0x1.a39ef35793c76p-39;        // ln2 / 64 - kL1
-  const double xc = fmin(fmax(x, -800.0), 709.8);  // -inf -> -800 -> 0; NaN -> -800, selected below
+  const double xc = fmin(fmax(x, -800.0), 709.8);  // -inf -> -800 -> 0; NaN -> -800
   const double kd = rint(xc * kInvL);
   const int k = (int)kd;
   double r = fma(-kd, kL1, xc);
@@ -40,7 +43,11 @@ __host__ __device__ inline double fast_exp(double x, const double* tab) {
   q = fma(q, r, 0.5);
   q = q * r * r + r;
   const double t = tab[j];
-  const double v = ldexp(fma(t, q, t), m);
+  return ldexp(fma(t, q, t), m);
+}
+
+__host__ __device__ inline double fast_exp(double x, const double* tab) {
+  const double v = fast_exp_finite(x, tab);
   return x != x ? x : v;
 }
 

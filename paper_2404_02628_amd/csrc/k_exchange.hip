@@ -51,6 +51,8 @@
 // solves the scaled in-block triangular system by forward substitution with lane broadcasts,
 // four rows per round; G_i = D_i + log w_i; (5) the in-block weighted payloads.  The scaled
 // unknowns satisfy 1 <= w_i <= 2^64, so nothing overflows whatever the range of the weights.
+#include <type_traits>
+
 #include "pimd_internal.h"
 #include "device_util.h"
 #include "fast_exp.h"
@@ -126,12 +128,15 @@ __device__ inline double term_of(const RowCtx& rc, const double (&pi)[D], const 
   d2 = 0.0;
 #pragma unroll
   for (int c = 0; c < D; ++c) { const double t = pi[c] - qv[c]; d2 = fma(t, t, d2); }
-  return fma(-rc.bc, d2, rc.rowc + r4.w) + xi_term<XM>(rc.i - 1 - j, rc.lnxi);
+  if constexpr (XM == kXiOne) return fma(-rc.bc, d2, rc.rowc + r4.w);
+  else return fma(-rc.bc, d2, rc.rowc + r4.w) + xi_term<XM>(rc.i - 1 - j, rc.lnxi);
 }
 
-// Sum of exp(t_j - R) over columns [ja, jb) with payload sums (q_j and |p_i - q_j|^2),
-// two interleaved accumulator sets, records prefetched one round ahead.
-template <int D, int XM>
+// Sum of exp(t_j - R) over columns [ja, jb) with payload sums (q_j, and with SP the cycle's
+// spring payload |p_i - q_j|^2 + lam_{i-1} - lam_j, which only the estimators need), two
+// interleaved accumulator sets, records prefetched one group ahead.  Whole pairs of four-column
+// groups run without masks; the at most seven columns left over run in masked groups.
+template <int D, int XM, bool SP>
 __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], double R, const double4* __restrict__ rec,
                                   const double* __restrict__ lam, int ja, int jb, const double* tab, double& s_out,
                                   double (&P)[D + 1]) {
@@ -140,43 +145,48 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int q = 0; q <= D; ++q) pq[h][q] = 0.0;
-  auto ld = [&](double4 (&dst)[4], double (&dl)[4], int j0) {
+  auto ld = [&](double4 (&dst)[4], double (&dl)[4], int j0, auto clamped) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      dst[u] = rec[min(j0 + u, jb - 1)];
-      dl[u] = lam[min(j0 + u, jb - 1)];
+      const int j = decltype(clamped)::value ? min(j0 + u, jb - 1) : j0 + u;
+      dst[u] = rec[j];
+      dl[u] = SP ? lam[j] : 0.0;
     }
   };
   // the reference enters the row constant once instead of every term
   const RowCtx rr{rc.i, rc.rowc - R, rc.bc, rc.lnxi, rc.lrow};
-  // groups of four columns; only the last group can be partial, and only it masks its terms
-  auto group = [&](const double4 (&g)[4], const double (&gl)[4], int j0) {
-    const bool full = j0 + 4 <= jb;
+  auto group = [&](const double4 (&g)[4], const double (&gl)[4], int j0, auto masked) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = j0 + u;
       double d2;
       double t = term_of<D, XM>(rr, pi, g[u], j, d2);   // t_{i,j} - R
-      if (!full && j >= jb) t = -INFINITY;
-      const double e = fast_exp(t, tab);
+      if constexpr (decltype(masked)::value) {
+        if (j >= jb) t = -INFINITY;
+      }
+      const double e = fast_exp_finite(t, tab);
       const int h = u & 1;
       s[h] += e;
       const double qv[3] = {g[u].x, g[u].y, g[u].z};
 #pragma unroll
       for (int c = 0; c < D; ++c) pq[h][c] = fma(e, qv[c], pq[h][c]);
-      pq[h][D] = fma(e, d2 + (rr.lrow - gl[u]), pq[h][D]);
+      if constexpr (SP) pq[h][D] = fma(e, d2 + (rr.lrow - gl[u]), pq[h][D]);
     }
   };
   // two record buffers in turn, each loaded one group ahead (no register copies between groups)
   double4 bufA[4], bufB[4];
   double lamA[4], lamB[4];
-  if (ja < jb) ld(bufA, lamA, ja);
-  for (int j0 = ja; j0 < jb; j0 += 8) {
-    if (j0 + 4 < jb) ld(bufB, lamB, j0 + 4);
-    group(bufA, lamA, j0);
-    if (j0 + 4 >= jb) break;
-    if (j0 + 8 < jb) ld(bufA, lamA, j0 + 8);
-    group(bufB, lamB, j0 + 4);
+  const int jf = ja + (jb - ja) / 8 * 8;
+  if (ja < jf) ld(bufA, lamA, ja, std::false_type{});
+  for (int j0 = ja; j0 < jf; j0 += 8) {
+    ld(bufB, lamB, j0 + 4, std::false_type{});
+    group(bufA, lamA, j0, std::false_type{});
+    if (j0 + 8 < jf) ld(bufA, lamA, j0 + 8, std::false_type{});
+    group(bufB, lamB, j0 + 4, std::false_type{});
+  }
+  for (int j0 = jf; j0 < jb; j0 += 4) {
+    ld(bufA, lamA, j0, std::true_type{});
+    group(bufA, lamA, j0, std::true_type{});
   }
   s_out = s[0] + s[1];
 #pragma unroll
@@ -185,7 +195,7 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
 
 // Same sums with a running maximum m (result = exp(m) * (s, P)); used when a term exceeds the
 // fixed reference by more than the double range.
-template <int D, int XM>
+template <int D, int XM, bool SP>
 __device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], const double4* __restrict__ rec,
                                    const double* __restrict__ lam, int ja, int jb, const double* tab, double& m_out,
                                    double& s_out, double (&P)[D + 1]) {
@@ -196,7 +206,7 @@ __device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], cons
     const double4 r4 = rec[j];
     double d2;
     const double t = term_of<D, XM>(rc, pi, r4, j, d2);
-    const double v = d2 + (rc.lrow - lam[j]);
+    const double v = SP ? d2 + (rc.lrow - lam[j]) : 0.0;
     const double dl = t - m;
     const double e = fast_exp(-fabs(dl), tab);
     const double qv[3] = {r4.x, r4.y, r4.z};
@@ -219,16 +229,16 @@ __device__ inline void bulk_online(const RowCtx& rc, const double (&pi)[D], cons
   for (int q = 0; q <= D; ++q) P[q] = pq[q];
 }
 
-template <int D, int XM>
+template <int D, int XM, bool SP>
 __device__ inline void bulk_rows(const RowCtx& rc, const double (&pi)[D], double R, const double4* __restrict__ rec,
                                  const double* __restrict__ lam, int ja, int jb, const double* tab, double& m,
                                  double& s, double (&P)[D + 1]) {
-  bulk_fixed<D, XM>(rc, pi, R, rec, lam, ja, jb, tab, s, P);
+  bulk_fixed<D, XM, SP>(rc, pi, R, rec, lam, ja, jb, tab, s, P);
   m = R;
   bool bad = !isfinite(s);
 #pragma unroll
   for (int q = 0; q <= D; ++q) bad = bad || !isfinite(P[q]);
-  if (__any(bad)) bulk_online<D, XM>(rc, pi, rec, lam, ja, jb, tab, m, s, P);
+  if (__any(bad)) bulk_online<D, XM, SP>(rc, pi, rec, lam, ja, jb, tab, m, s, P);
 }
 
 template <int D, int XM>
@@ -433,7 +443,7 @@ struct PipeRows {
 // sh.Wl, row data pi of that block): the term of column s in row i is exp(D_i) c_{i,s} w_s.  The
 // waves w >= W0 split the 64 columns (W0 = 0: consecutive runs of kCols; otherwise with stride
 // kWaves - W0) and store their sums in qp[w].
-template <int D, int W0, class SH>
+template <int D, int W0, bool SP, class SH>
 __device__ inline void block_payloads(SH& sh, const double* __restrict__ Am, int curp, const double (&pi)[D],
                                       double lrow, const double* __restrict__ lamblk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -451,7 +461,7 @@ __device__ inline void block_payloads(SH& sh, const double* __restrict__ Am, int
       d2 = fma(t, t, d2);
       Q[c] = fma(coef, qv[c], Q[c]);
     }
-    Q[D] = fma(coef, d2 + (lrow - lamblk[sc]), Q[D]);
+    if constexpr (SP) Q[D] = fma(coef, d2 + (lrow - lamblk[sc]), Q[D]);
   };
   if constexpr (W0 == 0) {   // kCols consecutive columns per wave
 #pragma unroll
@@ -499,7 +509,7 @@ __device__ inline void write_avg_kept(const SH& sh, const PipeRows<D>& pr, int s
 // prev_rows) are formed by waves 2.. while wave 0 combines and runs the max-plus pass, and wave 2
 // writes that block's row averages while wave 0 substitutes, so neither sits on the chain; the
 // caller alternates two coefficient buffers and forms the last block's payloads after the loop.
-template <int D, bool PIPE, class SH, class Idle, class PrevRows>
+template <int D, bool PIPE, bool SP, class SH, class Idle, class PrevRows>
 __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int cur, int N, bool valid,
                                    double4* __restrict__ rec, double* __restrict__ G, double* __restrict__ av,
                                    long long npp, const double (&pi)[D], double lrow, const double* __restrict__ lam,
@@ -537,7 +547,7 @@ __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int
   } else if (PIPE && blk > 0) {
     double pp[D], plr;
     prev_rows(pp, plr);   // row data of the previous block (reloaded: nothing is kept in registers)
-    block_payloads<D, 2>(sh, Am_prev, cur ^ 1, pp, plr, lam + (blk - 1) * kTile);
+    block_payloads<D, 2, SP>(sh, Am_prev, cur ^ 1, pp, plr, lam + (blk - 1) * kTile);
   }
   __syncthreads();
   scaled_coefficients<D>(sh, Am);
@@ -562,7 +572,7 @@ __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int
   if (!PIPE) {
     // (5) weighted payloads of the in-block terms, kCols consecutive columns per wave
     // (normalised by wave 0 when it writes the averages at the start of the next block)
-    block_payloads<D, 0>(sh, Am, cur, pi, lrow, lam + blk * kTile);
+    block_payloads<D, 0, SP>(sh, Am, cur, pi, lrow, lam + blk * kTile);
   }
 }
 
@@ -641,7 +651,7 @@ __device__ inline void link_prefix(const RecMap<D>& mp, double inv_c, double* __
 
 // One workgroup per replica and direction (batched replicas fill the machine).  Workgroups 2k
 // and 2k + 1 serve replica order[k]: the plan lists replicas in index order or longest first.
-template <int D>
+template <int D, bool SP>
 __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __restrict__ reps,
                                                            const double* __restrict__ ends,
                                                            const double* __restrict__ link,
@@ -725,9 +735,9 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
     if (bulk_ok && jend > jlo) {
       const int per = (jend - jlo + kBatchWaves - 1) / kBatchWaves;
       const int ja = min(jend, jlo + wave * per), jb = min(jend, ja + per);
-      if (xm == kXiOne) bulk_rows<D, kXiOne>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
-      else if (xm == kXiZero) bulk_rows<D, kXiZero>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
-      else bulk_rows<D, kXiGen>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
+      if (xm == kXiOne) bulk_rows<D, kXiOne, SP>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
+      else if (xm == kXiZero) bulk_rows<D, kXiZero, SP>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
+      else bulk_rows<D, kXiGen, SP>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
     }
     sh.pm[wave][lane] = m;
     sh.ps[wave][lane] = s;
@@ -735,7 +745,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __
     for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = P[q];
     inblock_alpha<D>(sh, sh.Am, cur, blk, i, pi, rho, valid, bc, lnxi, mp.bnd);
     const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
-    solve_block<D, false>(sh, sh.Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, nullptr, 0, cy, [] {},
+    solve_block<D, false, SP>(sh, sh.Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, nullptr, 0, cy, [] {},
                           sh.Am, [](double (&)[D], double&) {}, nullptr);
   }
   __syncthreads();
@@ -778,7 +788,7 @@ __device__ inline bool wait_epoch(const int* flag, int epoch, int* err) {
 
 // Folds columns [j0, j0 + n) into the running log-sum-exp (m, s, P): one rescale per slice.
 // `recs` points at the record of column j0 (global or LDS).
-template <int D, int XM, int NC>
+template <int D, int XM, int NC, bool SP>
 __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const double4* recs, const double* lams,
                                   int j0, int n, const double* tab, double& m, double& s, double (&P)[D + 1]) {
   double t[NC], d2[NC];
@@ -788,7 +798,7 @@ __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const
   for (int u = 0; u < NC; ++u) {
     r[u] = recs[min(u, n - 1)];
     t[u] = term_of<D, XM>(rc, pi, r[u], j0 + u, d2[u]);
-    d2[u] += rc.lrow - lams[min(u, n - 1)];   // payload: closing distance plus the cycle's links
+    if (SP) d2[u] += rc.lrow - lams[min(u, n - 1)];   // payload: closing distance plus the cycle's links
     if (u >= n) t[u] = -INFINITY;
     mt = fmax(mt, t[u]);
   }
@@ -800,25 +810,25 @@ __device__ inline void slice_fold(const RowCtx& rc, const double (&pi)[D], const
   m = M;
 #pragma unroll
   for (int u = 0; u < NC; ++u) {
-    const double e = fast_exp(t[u] - M, tab);
+    const double e = fast_exp_finite(t[u] - M, tab);
     s += e;
     const double qv[3] = {r[u].x, r[u].y, r[u].z};
 #pragma unroll
     for (int c = 0; c < D; ++c) P[c] = fma(e, qv[c], P[c]);
-    P[D] = fma(e, d2[u], P[D]);
+    if constexpr (SP) P[D] = fma(e, d2[u], P[D]);
   }
 }
 
-template <int D, int NC>
+template <int D, int NC, bool SP>
 __device__ inline void fold_any(int xm, const RowCtx& rc, const double (&pi)[D], const double4* recs,
                                 const double* lams, int j0, int n, const double* tab, double& m, double& s,
                                 double (&P)[D + 1]) {
-  if (xm == kXiOne) slice_fold<D, kXiOne, NC>(rc, pi, recs, lams, j0, n, tab, m, s, P);
-  else if (xm == kXiZero) slice_fold<D, kXiZero, NC>(rc, pi, recs, lams, j0, n, tab, m, s, P);
-  else slice_fold<D, kXiGen, NC>(rc, pi, recs, lams, j0, n, tab, m, s, P);
+  if (xm == kXiOne) slice_fold<D, kXiOne, NC, SP>(rc, pi, recs, lams, j0, n, tab, m, s, P);
+  else if (xm == kXiZero) slice_fold<D, kXiZero, NC, SP>(rc, pi, recs, lams, j0, n, tab, m, s, P);
+  else slice_fold<D, kXiGen, NC, SP>(rc, pi, recs, lams, j0, n, tab, m, s, P);
 }
 
-template <int D, bool PIPE>
+template <int D, bool PIPE, bool SP>
 __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev* __restrict__ reps,
                                                                 const double* __restrict__ ends,
                                                                 const double* __restrict__ link,
@@ -903,7 +913,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
       if (blk >= 1 && bulk_ok) {
         const int j0 = (blk - 1) * kTile + wave * kCoopCols, js = max(j0, jlo);
         if (js < j0 + kCoopCols)
-          fold_any<D, kCoopCols>(xm, rc, pi, sh.col[cur ^ 1] + wave * kCoopCols + (js - j0), lam + js, js,
+          fold_any<D, kCoopCols, SP>(xm, rc, pi, sh.col[cur ^ 1] + wave * kCoopCols + (js - j0), lam + js, js,
                                  j0 + kCoopCols - js, sh.tab, m, s, P);
       }
       if (bulk_ok && have_part && hs > 0.0) {
@@ -936,7 +946,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
           }
         }
       };
-      solve_block<D, PIPE>(sh, Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, panel_ready + blk, epoch,
+      solve_block<D, PIPE, SP>(sh, Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, panel_ready + blk, epoch,
                            cy, fetch_next, Am_prev, [&](double (&pp)[D], double& lr) { rows_of(blk - 1, pp, lr); },
                            &prow);
     }
@@ -947,7 +957,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
       if (wave >= 2) {
         double pp[D], lr;
         rows_of(nblk - 1, pp, lr);
-        block_payloads<D, 2>(sh, lastc ? am_alt : sh.Am, lastc, pp, lr, lam + (nblk - 1) * kTile);
+        block_payloads<D, 2, SP>(sh, lastc ? am_alt : sh.Am, lastc, pp, lr, lam + (nblk - 1) * kTile);
       }
       __syncthreads();
       if (wave == 2) write_avg_kept<D, 2>(sh, prow, lastc, nblk - 1, N, av, npp);
@@ -1000,7 +1010,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
       }
       const int j0 = c * kTile + wave * kCoopCols, js = max(j0, jlo);
       if (bulk_ok && js < j0 + kCoopCols)
-        fold_any<D, kCoopCols>(xm, rc, pi, rec + js, lam + js, js, j0 + kCoopCols - js, sh.tab, m, s, P);
+        fold_any<D, kCoopCols, SP>(xm, rc, pi, rec + js, lam + js, js, j0 + kCoopCols - js, sh.tab, m, s, P);
     }
     sh.pm[wave][lane] = m;
     sh.ps[wave][lane] = s;
@@ -1031,14 +1041,17 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   }
 }
 
-hipError_t launch_recursion(const Dims& d, const DevPtrs& w, hipStream_t s) {
+hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, hipStream_t s) {
   dim3 grid((unsigned)(2 * d.R)), block(64 * kBatchWaves);
-#define L(DD) hipLaunchKernelGGL(k_recursion<DD>, grid, block, 0, s, w.reps, w.ends, w.link, w.gf, w.gb, w.colrec, w.avg, \
-                              w.lam, w.reporder)
-  switch (d.D) {
-    case 1: L(1); break;
-    case 2: L(2); break;
-    case 3: L(3); break;
+#define L(DD, SPV) hipLaunchKernelGGL((k_recursion<DD, SPV>), grid, block, 0, s, w.reps, w.ends, w.link, w.gf, w.gb, \
+                                    w.colrec, w.avg, w.lam, w.reporder)
+  switch (d.D * 2 + (sp ? 1 : 0)) {
+    case 2: L(1, false); break;
+    case 3: L(1, true); break;
+    case 4: L(2, false); break;
+    case 5: L(2, true); break;
+    case 6: L(3, false); break;
+    case 7: L(3, true); break;
     default: return hipErrorInvalidValue;
   }
 #undef L
@@ -1052,7 +1065,7 @@ constexpr int kPipeMinBlocks = 64;
 
 static bool coop_pipelined(int maxn) { return (maxn + 1 + kTile - 1) / kTile >= kPipeMinBlocks; }
 
-template <int D, bool PIPE>
+template <int D, bool PIPE, bool SP>
 static hipError_t launch_coop_d(const Dims& d, const DevPtrs& w, int H, hipStream_t s) {
   int nchains = 2 * d.R;
   dim3 grid((unsigned)(nchains * (1 + H))), block(64 * kCoopWaves);
@@ -1069,15 +1082,22 @@ static hipError_t launch_coop_d(const Dims& d, const DevPtrs& w, int H, hipStrea
   int* err = w.err;
   void* args[] = {(void*)&reps, (void*)&ends, (void*)&link, (void*)&gf, (void*)&gb, (void*)&colrec, (void*)&avg,
                   (void*)&lamall, (void*)&flags, (void*)&partial, (void*)&err, (void*)&nchains, (void*)&H};
-  return hipLaunchCooperativeKernel((const void*)k_recursion_coop<D, PIPE>, grid, block, args, 0, s);
+  return hipLaunchCooperativeKernel((const void*)k_recursion_coop<D, PIPE, SP>, grid, block, args, 0, s);
 }
 
-hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, hipStream_t s) {
-  const bool pipe = coop_pipelined(d.maxn);
-  switch (d.D) {
-    case 1: return pipe ? launch_coop_d<1, true>(d, w, helpers, s) : launch_coop_d<1, false>(d, w, helpers, s);
-    case 2: return pipe ? launch_coop_d<2, true>(d, w, helpers, s) : launch_coop_d<2, false>(d, w, helpers, s);
-    case 3: return pipe ? launch_coop_d<3, true>(d, w, helpers, s) : launch_coop_d<3, false>(d, w, helpers, s);
+template <int D, bool SP>
+static hipError_t launch_coop_pipe(const Dims& d, const DevPtrs& w, int helpers, hipStream_t s) {
+  return coop_pipelined(d.maxn) ? launch_coop_d<D, true, SP>(d, w, helpers, s) : launch_coop_d<D, false, SP>(d, w, helpers, s);
+}
+
+hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, bool sp, hipStream_t s) {
+  switch (d.D * 2 + (sp ? 1 : 0)) {
+    case 2: return launch_coop_pipe<1, false>(d, w, helpers, s);
+    case 3: return launch_coop_pipe<1, true>(d, w, helpers, s);
+    case 4: return launch_coop_pipe<2, false>(d, w, helpers, s);
+    case 5: return launch_coop_pipe<2, true>(d, w, helpers, s);
+    case 6: return launch_coop_pipe<3, false>(d, w, helpers, s);
+    case 7: return launch_coop_pipe<3, true>(d, w, helpers, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1085,8 +1105,12 @@ hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, h
 template <int D, bool PIPE>
 static int coop_blocks_per_cu() {
   int n = 0;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<D, PIPE>, 64 * kCoopWaves, 0) == hipSuccess
-             ? n : 0;
+  int n2 = 0;
+  const bool ok = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_recursion_coop<D, PIPE, true>, 64 * kCoopWaves, 0) ==
+                      hipSuccess &&
+                  hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, k_recursion_coop<D, PIPE, false>, 64 * kCoopWaves, 0) ==
+                      hipSuccess;
+  return ok ? std::min(n, n2) : 0;
 }
 
 int recursion_coop_max_blocks_per_cu(int D, int maxn) {
