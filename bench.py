@@ -103,15 +103,16 @@ def algorithmic_work(kind, systems, P, D, precision="mixed"):
         # link and internal energy ((2D + 2) x 8 B), spread over its D P dofs
         per = 16 + (4 if precision == "mixed" else 0) + (2 * D + 2) * 8 / (D * P)
         return "hbm", dofs, per, "GB/s", PEAK_HBM_GBS
+    # the chain positions are kept as per-wavefront sums (a few bytes per 64 dofs, not counted)
     if kind == "integrate_first":
-        # read x, p, f, eta[4], veta[4]; write x, p, eta[4], veta[4]
-        return "hbm", dofs, 8 * (11 + 10), "GB/s", PEAK_HBM_GBS
+        # read x, p, f, v_eta[4]; write x, p, v_eta[4]
+        return "hbm", dofs, 8 * (7 + 6), "GB/s", PEAK_HBM_GBS
     if kind == "integrate_second":
-        # read p, f, f_pair, eta[4], veta[4]; write p, f, eta[4], veta[4]
-        return "hbm", dofs, 8 * (11 + 10), "GB/s", PEAK_HBM_GBS
+        # read p, f, f_pair, v_eta[4]; write p, f, v_eta[4]
+        return "hbm", dofs, 8 * (7 + 6), "GB/s", PEAK_HBM_GBS
     if kind == "integrate_fused":
-        # read x, p, f, f_pair, eta[4], veta[4]; write x, p, eta[4], veta[4]
-        return "hbm", dofs, 8 * (12 + 10), "GB/s", PEAK_HBM_GBS
+        # read x, p, f, f_pair, v_eta[4]; write x, p, v_eta[4]
+        return "hbm", dofs, 8 * (8 + 6), "GB/s", PEAK_HBM_GBS
     if kind == "exchange_forces":
         # per particle: potentials and links (7), row averages (2D + 1), end beads and their
         # neighbours (6D) read, bead 1 and bead P forces read and written (4D)  ->  (8 + 12D) x 8 B

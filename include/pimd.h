@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define PIMD_ABI_VERSION 6
+#define PIMD_ABI_VERSION 7
 
 typedef enum {
     PIMD_OK = 0,
@@ -195,8 +195,12 @@ pimd_status pimd_destroy(pimd_ctx* ctx);
 pimd_status pimd_init_system(pimd_ctx* ctx, const double* pos_sigma, const uint64_t* seeds);
 
 /* Sets positions x and (optionally) momenta p of replica r, layout [dim][P][N].
- * nhc (optional) holds the thermostat state as [2][nhc_len][dim][P][N]
- * (positions eta, then velocities v_eta); NULL zeroes it (p NULL zeroes p).
+ * nhc (optional) holds the thermostat state: the chain velocities v_eta as
+ * [nhc_len][dim][P][N], followed by ONE double, the sum of all chain positions eta
+ * of the replica (over its coordinates and chain elements).  The chain positions
+ * never act on the dynamics; they enter only the conserved quantity, through
+ * kT times that sum, so the library keeps the sum instead of every eta.  NULL
+ * zeroes the thermostat state (p NULL zeroes p).
  * `where` says whether the pointers are host or device memory.  Invalidates the
  * forces of replica r until the next evaluation, and restarts a halted run
  * (a replica that is still non-finite halts it again at the next evaluation).
@@ -206,7 +210,11 @@ pimd_status pimd_init_system(pimd_ctx* ctx, const double* pos_sigma, const uint6
 pimd_status pimd_set_state(pimd_ctx* ctx, int32_t r, const double* x, const double* p,
                            const double* nhc, pimd_mem where);
 
-/* Copies the state of replica r out (any pointer may be NULL).  Synchronous.
+/* Copies the state of replica r out (any pointer may be NULL; nhc in the layout of
+ * pimd_set_state, nhc_len*dim*P*N + 1 doubles).  Synchronous.  The library holds the
+ * chain positions' sum as partial sums; reading nhc folds them into the one value
+ * returned, so the context and any context restarted from the returned state
+ * continue bit for bit alike.
  * Reports a halted run (PIMD_ERR_NONFINITE, PIMD_ERR_DEVICE) after copying. */
 pimd_status pimd_get_state(pimd_ctx* ctx, int32_t r, double* x, double* p, double* nhc,
                            pimd_mem where);

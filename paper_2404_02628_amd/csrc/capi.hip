@@ -189,8 +189,10 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
       if (lists) pl.springwork.push_back(make_int4(r, l0, 0, 0));
     R.spw1 = nspring;
     R.rw0 = R.spw0; R.rw1 = R.spw1;
+    R.iw0 = nint;
     for (long long d0 = 0; d0 < R.ndof; d0 += kIntBlock, ++nint)
       if (lists) pl.intwork.push_back(make_int4(r, (int)d0, 0, 0));
+    R.iw1 = nint;
     if (lists) pl.reps[r] = R;
     if (r == 0) pl.rep0 = R;
   }
@@ -225,6 +227,13 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
     pl.persistent = pl.persistent && persistent_fits(d.D, d.P, c->replicas[r].n);
     pl.persist_maxdof = std::max(pl.persist_maxdof, d.D * d.P * c->replicas[r].n);
   }
+  for (int r = 0; r < (lists ? d.R : 0); ++r) {
+    RepDev& R = pl.reps[r];
+    R.es0 = pl.persistent ? R.dof : R.iw0 * kEtaSlots;
+    R.es1 = pl.persistent ? R.dof + R.ndof : R.iw1 * kEtaSlots;
+  }
+  pl.rep0.es0 = pl.persistent ? pl.rep0.dof : pl.rep0.iw0 * kEtaSlots;
+  pl.rep0.es1 = pl.persistent ? pl.rep0.dof + pl.rep0.ndof : pl.rep0.iw1 * kEtaSlots;
   d.nspringwg = nspring;
   d.npairwork = npair;
   d.nreducewg = d.nspringwg;
@@ -234,7 +243,10 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
   sz[S_REPS] = sizeof(RepDev) * d.R;
   sz[S_X] = sz[S_P] = sz[S_F] = sz[S_FPAIR] = 8ull * G;
   sz[S_XS] = 4ull * XS;
-  sz[S_ETA] = sz[S_VETA] = 8ull * G * d.M;
+  // chain-position sums: per dof on the persistent path (the sums of a coordinate stay with its
+  // thread across launches), per integrator wavefront on the streaming path
+  sz[S_ETA] = d.M == 0 ? 0 : (pl.persistent ? 8ull * G : 8ull * kEtaSlots * nint);
+  sz[S_VETA] = 8ull * G * d.M;
   sz[S_ENDS] = 8ull * 2 * d.D * NP;
   sz[S_LINK] = sz[S_EINT] = sz[S_GF] = sz[S_GB] = 8ull * NP;
   sz[S_COLREC] = 32ull * 2 * NP;
@@ -274,7 +286,7 @@ void carve(char* ws, const size_t* off, DevPtrs& w) {
   w.f = (double*)(ws + off[S_F]);
   w.fpair = (double*)(ws + off[S_FPAIR]);
   w.xs = (float*)(ws + off[S_XS]);
-  w.eta = (double*)(ws + off[S_ETA]);
+  w.etasum = (double*)(ws + off[S_ETA]);
   w.veta = (double*)(ws + off[S_VETA]);
   w.ends = (double*)(ws + off[S_ENDS]);
   w.link = (double*)(ws + off[S_LINK]);
@@ -679,14 +691,16 @@ pimd_status pimd_set_state(pimd_ctx* c, int32_t r, const double* x, const double
   HIPCHK(hipMemcpyAsync(c->w.x + R.dof, x, nb, kind_in(where), c->s));
   if (p) HIPCHK(hipMemcpyAsync(c->w.p + R.dof, p, nb, kind_in(where), c->s));
   else HIPCHK(hipMemsetAsync(c->w.p + R.dof, 0, nb, c->s));
+  // thermostat: chain velocities, then the chain positions' sum into the replica's first slot
   for (int k = 0; k < d.M; ++k) {
-    if (nhc) {
-      HIPCHK(hipMemcpyAsync(c->w.eta + (long long)k * d.G + R.dof, nhc + (size_t)k * R.ndof, nb, kind_in(where), c->s));
-      HIPCHK(hipMemcpyAsync(c->w.veta + (long long)k * d.G + R.dof, nhc + (size_t)(d.M + k) * R.ndof, nb, kind_in(where), c->s));
-    } else {
-      HIPCHK(hipMemsetAsync(c->w.eta + (long long)k * d.G + R.dof, 0, nb, c->s));
-      HIPCHK(hipMemsetAsync(c->w.veta + (long long)k * d.G + R.dof, 0, nb, c->s));
-    }
+    if (nhc) HIPCHK(hipMemcpyAsync(c->w.veta + (long long)k * d.G + R.dof, nhc + (size_t)k * R.ndof, nb, kind_in(where), c->s));
+    else HIPCHK(hipMemsetAsync(c->w.veta + (long long)k * d.G + R.dof, 0, nb, c->s));
+  }
+  if (d.M > 0) {
+    double* slots = c->w.etasum + R.es0;
+    const size_t nslots = (size_t)(R.es1 - R.es0);
+    HIPCHK(hipMemsetAsync(slots, 0, sizeof(double) * nslots, c->s));
+    if (nhc) HIPCHK(hipMemcpyAsync(slots, nhc + (size_t)d.M * R.ndof, sizeof(double), kind_in(where), c->s));
   }
   HIPCHK(hipStreamSynchronize(c->s));
   c->forces_valid = false;
@@ -703,11 +717,24 @@ pimd_status pimd_get_state(pimd_ctx* c, int32_t r, double* x, double* p, double*
   const size_t nb = sizeof(double) * (size_t)R.ndof;
   if (x) HIPCHK(hipMemcpyAsync(x, c->w.x + R.dof, nb, kind_out(where), c->s));
   if (p) HIPCHK(hipMemcpyAsync(p, c->w.p + R.dof, nb, kind_out(where), c->s));
-  if (nhc)
-    for (int k = 0; k < d.M; ++k) {
-      HIPCHK(hipMemcpyAsync(nhc + (size_t)k * R.ndof, c->w.eta + (long long)k * d.G + R.dof, nb, kind_out(where), c->s));
-      HIPCHK(hipMemcpyAsync(nhc + (size_t)(d.M + k) * R.ndof, c->w.veta + (long long)k * d.G + R.dof, nb, kind_out(where), c->s));
-    }
+  if (nhc && d.M > 0) {
+    for (int k = 0; k < d.M; ++k)
+      HIPCHK(hipMemcpyAsync(nhc + (size_t)k * R.ndof, c->w.veta + (long long)k * d.G + R.dof, nb, kind_out(where), c->s));
+    // the sum of the chain positions, from the replica's slots in a fixed order
+    std::vector<double> slots((size_t)(R.es1 - R.es0));
+    HIPCHK(hipMemcpyAsync(slots.data(), c->w.etasum + R.es0, sizeof(double) * slots.size(), hipMemcpyDeviceToHost,
+                          c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    double total = 0.0;
+    for (double v : slots) total += v;
+    HIPCHK(hipMemcpy(nhc + (size_t)d.M * R.ndof, &total, sizeof(double),
+                     where == PIMD_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    // fold the slots into the value returned, as pimd_set_state stores it: a context started
+    // from this state then adds the same increments to the same slots, bit for bit
+    std::fill(slots.begin(), slots.end(), 0.0);
+    slots[0] = total;
+    HIPCHK(hipMemcpy(c->w.etasum + R.es0, slots.data(), sizeof(double) * slots.size(), hipMemcpyHostToDevice));
+  }
   HIPCHK(hipStreamSynchronize(c->s));
   return check_status(c);
 }
@@ -731,7 +758,7 @@ pimd_status pimd_compute_forces_noalloc(const pimd_config* cfg, const double* x,
   // the caller's arrays; no momenta, thermostats, trace, density or debug output
   w.x = const_cast<double*>(x);
   w.f = f;
-  w.p = nullptr; w.eta = nullptr; w.veta = nullptr; w.trace = nullptr; w.tracecount = nullptr;
+  w.p = nullptr; w.etasum = nullptr; w.veta = nullptr; w.trace = nullptr; w.tracecount = nullptr;
   w.dens = nullptr; w.denssamples = nullptr; w.dbg = nullptr;
   Dims d = pl.d;
   d.M = 0;
@@ -959,6 +986,8 @@ pimd_status pimd_init_system(pimd_ctx* c, const double* pos_sigma, const uint64_
   if (st != PIMD_OK) return st;
   HIPCHK(hipMemcpyAsync(c->w.dbg, prm.data(), sizeof(double) * prm.size(), hipMemcpyHostToDevice, c->s));
   HIPCHK(launch_init_state(c->pl.d, c->w, c->w.dbg, c->s));
+  if (c->pl.d.M > 0)   // chains at rest: every chain-position sum to zero
+    HIPCHK(hipMemsetAsync(c->w.etasum, 0, c->pl.off[S_ETA + 1] - c->pl.off[S_ETA], c->s));
   HIPCHK(hipStreamSynchronize(c->s));
   c->forces_valid = false;
   c->has_state = true;

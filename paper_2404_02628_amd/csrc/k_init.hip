@@ -47,8 +47,7 @@ __global__ __launch_bounds__(kIntBlock) void k_init_state(const RepDev* __restri
                                                           const int4* __restrict__ work,
                                                           const double* __restrict__ params,
                                                           double* __restrict__ x, double* __restrict__ p,
-                                                          double* __restrict__ eta, double* __restrict__ veta,
-                                                          long long G, int M) {
+                                                          double* __restrict__ veta, long long G, int M) {
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
   const long long li = (long long)wk.y + threadIdx.x;
@@ -58,16 +57,13 @@ __global__ __launch_bounds__(kIntBlock) void k_init_state(const RepDev* __restri
   const unsigned long long seed = (unsigned long long)__double_as_longlong(params[2LL * wk.x + 1]);
   x[gi] = sigma * gaussian(seed, 0u, (unsigned long long)li);
   p[gi] = sqrt(R.mp / R.beta) * gaussian(seed, 1u, (unsigned long long)li);
-  for (int k = 0; k < M; ++k) {
-    eta[k * G + gi] = 0.0;
-    veta[k * G + gi] = 0.0;
-  }
+  for (int k = 0; k < M; ++k) veta[k * G + gi] = 0.0;
 }
 
 hipError_t launch_init_state(const Dims& d, const DevPtrs& w, const double* params, hipStream_t s) {
   if (d.nintwg == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_state, dim3((unsigned)d.nintwg), dim3(kIntBlock), 0, s, w.reps, w.intwork, params, w.x,
-                     w.p, w.eta, w.veta, d.G, d.M);
+                     w.p, w.veta, d.G, d.M);
   return hipGetLastError();
 }
 

@@ -21,14 +21,60 @@ namespace pimd {
 // mode 2: F = F + F_pair only (force evaluation without integration)
 // mode 3: second half of this step fused with the first half of the next one
 // A thread whose force, momentum or new position is not finite raises the non-finite status
-// word; once a status word is raised no integrator pass writes anything.
+// word; once a status word is raised no integrator pass writes anything.  The chain positions
+// are kept as sums only (they enter nothing but H'): each wave adds its increment to its own
+// slot of etasum, in a fixed order, so the sums are reproducible.
+// One degree of freedom of k_integrate, from its operands in registers: writes x, p, f and the
+// chain velocities; the chain-position increments go to es.
+template <int M, int MODE>
+__device__ inline void integrate_one(const RepDev& R, int rep, long long gi, double fv, double fpv, double pv,
+                                     double xv, double& es, double (&v)[M > 0 ? M : 1], double* __restrict__ x,
+                                     double* __restrict__ p, double* __restrict__ f, double* __restrict__ veta,
+                                     long long G, double hdt, const SyW& sy, const double* tab, int* status) {
+  constexpr bool kPair = MODE != 0;
+  constexpr bool kChain = M > 0 && MODE != 2;
+  if (kPair) fv = R.amp > 0.0 ? fv + fpv : fv;
+  if (MODE == 0) {
+    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    pv += hdt * fv;
+    const double xn = xv + R.dt_mp * pv;
+    if (!isfinite(fv) || !isfinite(xn)) status_nonfinite(status, rep);
+    x[gi] = xn;
+    p[gi] = pv;
+  } else {
+    // the total force is kept for readers of the last evaluation; in the fused pass the next
+    // evaluation overwrites it unread
+    if (MODE != 3) f[gi] = fv;
+    if (MODE == 2) {
+      if (!isfinite(fv)) status_nonfinite(status, rep);
+      return;
+    }
+    pv += hdt * fv;
+    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    double xn = 0.0;
+    if (MODE == 3) {
+      // second thermostat half-step of this step and first of the next, chain in registers
+      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy, tab);
+      pv += hdt * fv;
+      xn = xv + R.dt_mp * pv;
+      x[gi] = xn;
+    }
+    if (!isfinite(fv) || !isfinite(pv) || !isfinite(xn)) status_nonfinite(status, rep);
+    p[gi] = pv;
+  }
+  if (kChain) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) veta[k * G + gi] = v[k];
+  }
+}
+
 template <int M, int MODE>
 __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restrict__ reps,
                                                          const int4* __restrict__ work, double* __restrict__ x,
                                                          double* __restrict__ p, double* __restrict__ f,
-                                                         const double* __restrict__ fpair, double* __restrict__ eta,
-                                                         double* __restrict__ veta, long long G, SyW sy,
-                                                         int* status) {
+                                                         const double* __restrict__ fpair,
+                                                         double* __restrict__ etasum, double* __restrict__ veta,
+                                                         long long G, SyW sy, int* status) {
   __shared__ double tab[kExpTable];
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
@@ -43,61 +89,32 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
   constexpr bool kP = MODE != 2;
   constexpr bool kPair = MODE != 0;
   constexpr bool kChain = M > 0 && MODE != 2;
-  double fv = f[gi];
+  const double fv = f[gi];
   const double fpv = kPair ? fpair[gi] : 0.0;
-  double pv = kP ? p[gi] : 0.0;
+  const double pv = kP ? p[gi] : 0.0;
   const double xv = kX ? x[gi] : 0.0;
   const bool halted = status_halted(status);
-  double e[M > 0 ? M : 1], v[M > 0 ? M : 1];
+  double es = 0.0, v[M > 0 ? M : 1];
 #pragma unroll
-  for (int k = 0; k < (M > 0 ? M : 1); ++k) {
-    e[k] = kChain ? eta[k * G + gi] : 0.0;
-    v[k] = kChain ? veta[k * G + gi] : 0.0;
-  }
-  if (kChain) {
+  for (int k = 0; k < (M > 0 ? M : 1); ++k) v[k] = kChain ? veta[k * G + gi] : 0.0;
+  if constexpr (kChain) {
     if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
     __syncthreads();
-  }
-  if (!ok || halted) return;
-  if (kPair) fv = R.amp > 0.0 ? fv + fpv : fv;
-  if (MODE == 0) {
-    if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
-    pv += hdt * fv;
-    const double xn = xv + R.dt_mp * pv;
-    if (!isfinite(fv) || !isfinite(xn)) status_nonfinite(status, wk.x);
-    x[gi] = xn;
-    p[gi] = pv;
+    // every lane takes part in its wave's chain-position sum, so none leaves before it
+    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, tab,
+                                              status);
+    es = wave_sum(es);
+    if ((threadIdx.x & 63) == 0 && !halted) etasum[(long long)blockIdx.x * kEtaSlots + (threadIdx.x >> 6)] += es;
   } else {
-    // the total force is kept for readers of the last evaluation; in the fused pass the next
-    // evaluation overwrites it unread
-    if (MODE != 3) f[gi] = fv;
-    if (MODE == 2) {
-      if (!isfinite(fv)) status_nonfinite(status, wk.x);
-      return;
-    }
-    pv += hdt * fv;
-    if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
-    double xn = 0.0;
-    if (MODE == 3) {
-      // second thermostat half-step of this step and first of the next, chain in registers
-      if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, sy, tab);
-      pv += hdt * fv;
-      xn = xv + R.dt_mp * pv;
-      x[gi] = xn;
-    }
-    if (!isfinite(fv) || !isfinite(pv) || !isfinite(xn)) status_nonfinite(status, wk.x);
-    p[gi] = pv;
-  }
-  if (kChain) {
-#pragma unroll
-    for (int k = 0; k < M; ++k) { eta[k * G + gi] = e[k]; veta[k * G + gi] = v[k]; }
+    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, tab,
+                                              status);
   }
 }
 
 // One workgroup per replica: kinetic and thermostat energies over all dofs plus the
 // partial sums left by the spring, pair and end-bead kernels, in a fixed order.
 __global__ __launch_bounds__(256) void k_estimators(const RepDev* __restrict__ reps, const double* __restrict__ p,
-                                                    const double* __restrict__ eta, const double* __restrict__ veta,
+                                                    const double* __restrict__ etasum, const double* __restrict__ veta,
                                                     const double* __restrict__ gf,
                                                     const double* __restrict__ springpart,
                                                     const double* __restrict__ pairpart,
@@ -121,11 +138,16 @@ __global__ __launch_bounds__(256) void k_estimators(const RepDev* __restrict__ r
     acc[0] += 0.5 * pv * pv / R.mp;
     for (int k = 0; k < M; ++k) {
       const double v = veta[k * G + gi];
-      acc[1] += 0.5 * R.q * v * v + kT * eta[k * G + gi];
+      acc[1] += 0.5 * R.q * v * v;
     }
   }
   block_sum<2>(acc, lds);
   if (threadIdx.x != 0) return;
+  if (M > 0) {
+    double es = 0.0;
+    for (long long g = R.es0; g < R.es1; ++g) es += etasum[g];
+    acc[1] += kT * es;
+  }
   double eint = 0.0, lk = 0.0, ut = 0.0;
   for (long long g = R.spw0; g < R.spw1; ++g) {
     eint += springpart[4 * g + 0];
@@ -233,7 +255,7 @@ static hipError_t launch_integrate_mode(const Dims& d, const DevPtrs& w, hipStre
   dim3 grid((unsigned)d.nintwg), block(kIntBlock);
   const SyW sy = sy_weights(d.sy_order);
 #define L(MM) hipLaunchKernelGGL((k_integrate<MM, MODE>), grid, block, 0, s, w.reps, w.intwork, w.x, w.p, w.f, \
-                                 w.fpair, w.eta, w.veta, d.G, sy, w.err)
+                                 w.fpair, w.etasum, w.veta, d.G, sy, w.err)
   switch (d.M) {
     case 0: L(0); break; case 1: L(1); break; case 2: L(2); break; case 3: L(3); break;
     case 4: L(4); break; case 5: L(5); break; case 6: L(6); break; case 7: L(7); break; case 8: L(8); break;
@@ -256,7 +278,7 @@ hipError_t launch_integrate_fused(const Dims& d, const DevPtrs& w, hipStream_t s
 }
 
 hipError_t launch_estimators(const Dims& d, const DevPtrs& w, long long step, bool record, hipStream_t s) {
-  hipLaunchKernelGGL(k_estimators, dim3(d.R), dim3(256), 0, s, w.reps, w.p, w.eta, w.veta, w.gf, w.springpart,
+  hipLaunchKernelGGL(k_estimators, dim3(d.R), dim3(256), 0, s, w.reps, w.p, w.etasum, w.veta, w.gf, w.springpart,
                      w.pairpart, w.reducepart, w.rec, w.trace, w.tracecount, d.G, d.M, d.D, d.P, d.cap, step,
                      record ? 1 : 0, w.err);
   return hipGetLastError();

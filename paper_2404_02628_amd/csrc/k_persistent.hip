@@ -48,7 +48,7 @@ struct PersistShared {
 
 struct PersistArgs {
   const RepDev* reps;
-  double* x; double* p; double* f; double* eta; double* veta;
+  double* x; double* p; double* f; double* etasum; double* veta;
   double* ends; double* link; double* eint; double* gf; double* gb;
   double* rec; double* trace; long long* tracecount;
   unsigned long long* dens; long long* denssamples;
@@ -265,15 +265,18 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
   const long long G = A.G;
   if (t < kExpTable) sh.tab[t] = exp_table_entry(t);
   if (t == 0) sh.halt = status_halted(A.status) ? 1 : 0;
-  double xv = 0.0, pv = 0.0, fv = 0.0, e[M > 0 ? M : 1], v[M > 0 ? M : 1];
+  // es: the sum of this coordinate's chain positions (they only enter H', so one number per
+  // coordinate is kept instead of one per chain element; it stays with the thread across launches)
+  double xv = 0.0, pv = 0.0, fv = 0.0, es = 0.0, v[M > 0 ? M : 1];
 #pragma unroll
-  for (int k = 0; k < (M > 0 ? M : 1); ++k) { e[k] = 0.0; v[k] = 0.0; }
+  for (int k = 0; k < (M > 0 ? M : 1); ++k) v[k] = 0.0;
   if (own) {
     xv = A.x[gi];
     pv = A.p[gi];
     fv = A.f[gi];
 #pragma unroll
-    for (int k = 0; k < M; ++k) { e[k] = A.eta[k * G + gi]; v[k] = A.veta[k * G + gi]; }
+    for (int k = 0; k < M; ++k) v[k] = A.veta[k * G + gi];
+    if (M > 0) es = A.etasum[R.es0 + t];
   }
   __syncthreads();
   if (sh.halt) return;   // a halted run advances no further (uniform over the workgroup)
@@ -284,21 +287,22 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
     const long long stp = A.step0 + it + 1;
     const bool smp = A.sample_every > 0 && (stp % A.sample_every == 0);
     if (own) {
-      if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, A.sy, sh.tab);
+      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy, sh.tab);
       pv += hdt * fv;
       xv += R.dt_mp * pv;
     }
     fv = persist_evaluate<D>(sh, R, P, t, own, ca, cj, cl, xv, smp, en);
     if (own) {
       pv += hdt * fv;
-      if (M > 0) nhc_propagate(pv, R.inv_mp, e, v, M, R.inv_q, R.kT, hdt, A.sy, sh.tab);
+      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy, sh.tab);
     }
     if (smp) {
       double kv[2] = {0.0, 0.0};
       if (own) {
         kv[0] = 0.5 * pv * pv / R.mp;
 #pragma unroll
-        for (int k = 0; k < M; ++k) kv[1] += 0.5 * R.q * v[k] * v[k] + R.kT * e[k];
+        for (int k = 0; k < M; ++k) kv[1] += 0.5 * R.q * v[k] * v[k];
+        kv[1] += R.kT * es;
       }
       block_sum<2>(kv, sh.red);
       if (t == 0) {
@@ -357,7 +361,8 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
     A.p[gi] = pv;
     A.f[gi] = fv;
 #pragma unroll
-    for (int k = 0; k < M; ++k) { A.eta[k * G + gi] = e[k]; A.veta[k * G + gi] = v[k]; }
+    for (int k = 0; k < M; ++k) A.veta[k * G + gi] = v[k];
+    if (M > 0) A.etasum[R.es0 + t] = es;
   }
   if (!A.need_forces && A.nsteps == 0) return;   // no evaluation ran: nothing more to store
   if (t < N) {
@@ -383,7 +388,7 @@ hipError_t launch_persistent(const Dims& d, const DevPtrs& w, int maxdof, long l
                              int sample_every, bool need_forces, hipStream_t s) {
   PersistArgs A;
   A.reps = w.reps;
-  A.x = w.x; A.p = w.p; A.f = w.f; A.eta = w.eta; A.veta = w.veta;
+  A.x = w.x; A.p = w.p; A.f = w.f; A.etasum = w.etasum; A.veta = w.veta;
   A.ends = w.ends; A.link = w.link; A.eint = w.eint; A.gf = w.gf; A.gb = w.gb;
   A.rec = w.rec; A.trace = w.trace; A.tracecount = w.tracecount;
   A.dens = w.dens; A.denssamples = w.denssamples;

@@ -33,8 +33,10 @@ __device__ inline double chain_exp(double x, const double* tab) {
 // The chain forces are G_1 = (p^2/m' - kT)/Q and G_k = (Q v_{k-1}^2 - kT)/Q = v_{k-1}^2 - kT/Q,
 // evaluated with precomputed reciprocals.  The scale factor exp(-h v_{k+1}/4) of element k is
 // the same number in the inward and the outward sweep (v_{k+1} is not touched in between), so
-// it is computed once per sub-step.
-__device__ inline void nhc_propagate(double& p, double inv_mp, double* eta, double* v, int M, double inv_q,
+// it is computed once per sub-step.  The chain positions eta_k only enter the conserved quantity
+// H' (through kT sum_k eta_k), so the propagator adds their increments h v_k into one number,
+// eta_sum, instead of keeping every eta_k.
+__device__ inline void nhc_propagate(double& p, double inv_mp, double& eta_sum, double* v, int M, double inv_q,
                                      double kT, double tau, const SyW& sy, const double* tab) {
   const double kTq = kT * inv_q;
   for (int iw = 0; iw < sy.n; ++iw) {
@@ -50,7 +52,9 @@ __device__ inline void nhc_propagate(double& p, double inv_mp, double* eta, doub
       v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];
     }
     p *= chain_exp(-h * v[0], tab);
-    for (int k = 0; k < M; ++k) eta[k] += h * v[k];
+    double vs = 0.0;
+    for (int k = 0; k < M; ++k) vs += v[k];
+    eta_sum = fma(h, vs, eta_sum);
     for (int k = 0; k <= M - 2; ++k) {
       double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
       v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];

@@ -14,6 +14,7 @@ constexpr int kMaxNhc = 8;         // longest thermostat chain
 constexpr int kRec = 16;           // doubles per energy record
 constexpr int kSpringBlock = 256;  // particles per spring-kernel workgroup
 constexpr int kIntBlock = 256;     // degrees of freedom per integrator workgroup
+constexpr int kEtaSlots = kIntBlock / 64;   // chain-position sums per integrator work item (one per wave)
 
 // Energy record slots (per replica, and per trace sample).
 enum RecSlot {
@@ -35,6 +36,9 @@ struct RepDev {
   long long spw0, spw1;    // spring workgroups [spw0, spw1)
   long long pw0, pw1;      // pair work items [pw0, pw1)
   long long rw0, rw1;      // probability-reduce workgroups [rw0, rw1)
+  long long iw0, iw1;      // integrator work items [iw0, iw1)
+  long long es0, es1;      // this replica's chain-position sums etasum[es0, es1): kEtaSlots per integrator
+                           // work item, or one per dof when steps run in the persistent kernel
   double beta, hbar, mass, omega, xi, amp, width, dt, q, mp;
   double c;         // (1/2) m omega_P^2, omega_P = sqrt(P)/(beta hbar)
   double kappa;     // m omega_P^2
@@ -54,7 +58,10 @@ struct DevPtrs {
   RepDev* reps;
   double* x; double* p; double* f; double* fpair;
   float* xs;                   // FP32 shadow of x for the pair kernel, layout per replica [P][npad][dp]
-  double* eta; double* veta;   // [M][G]
+  double* etasum;              // sums of the chain positions eta over dofs and chain elements: per
+                               // integrator work item and wavefront ([nintwg][kEtaSlots]), or per dof
+                               // ([G]) for the persistent kernel
+  double* veta;                // [M][G] chain velocities
   double* ends;                // per replica: [2*dim][npp]  (a = first beads, then b = last beads)
   double* link;                // [npp]: c |b_l - a_{l+1}|^2, 0 for the last particle of each species
   double* eint;                // [npp]: internal spring energy of each ring

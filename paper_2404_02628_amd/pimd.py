@@ -325,14 +325,15 @@ class Context:
         shape = (s.dim, s.p, s.n)
         x = _f64(x, shape)
         p = None if p is None else _f64(p, shape)
-        nhc = None if nhc is None else _f64(nhc, (2, self.nhc_len) + shape)
+        nhc = None if nhc is None else _f64(nhc, (self.nhc_len * s.dim * s.p * s.n + 1,))
         pimd_set_state(self.h, r, x, p, nhc)
 
     def get_state(self, r: int):
         s = self.systems[r]
         shape = (s.dim, s.p, s.n)
         x, p = np.zeros(shape), np.zeros(shape)
-        nhc = np.zeros((2, self.nhc_len) + shape)
+        # thermostat: chain velocities [nhc_len][dim][P][N], then the sum of the chain positions
+        nhc = np.zeros(self.nhc_len * s.dim * s.p * s.n + 1)
         pimd_get_state(self.h, r, x, p, nhc if self.nhc_len else None)
         return x, p, nhc
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(lib):
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
     assert set(names) == set(lib.EXPORTED)
-    assert lib.pimd_abi_version() == 6
+    assert lib.pimd_abi_version() == 7
 
 
 def _cfg(lib, **over):

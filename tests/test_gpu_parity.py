@@ -177,12 +177,14 @@ def test_large_gauss_workload_matches_oracle(orc, mixed, start, sched):
         ctx.close()
 
 
-def test_short_trajectory_matches_oracle(orc):
-    """40 thermostatted velocity-Verlet steps from the same state stay together (FP64)."""
+@pytest.mark.parametrize("persistent", [True, False], ids=["persistent", "multi-kernel"])
+def test_short_trajectory_matches_oracle(orc, persistent):
+    """40 thermostatted velocity-Verlet steps from the same state stay together (FP64): positions,
+    momenta, chain velocities and the sum of the chain positions (all the library keeps of them)."""
     from paper_2404_02628_amd.pimd import Context
     s = System(n=8, p=12, dim=2, beta=3.0, xi=0.6, pair_amp=1.0, pair_width=0.5, sigma=0.5, seed=77)
     x, p = initial_state(s)
-    ctx = Context([s], precision="fp64", nhc_len=4)
+    ctx = Context([s], precision="fp64", nhc_len=4, persistent=persistent)
     try:
         ctx.set_state(0, x, p)
         ctx.step(40, 0)
@@ -198,7 +200,8 @@ def test_short_trajectory_matches_oracle(orc):
     orc.step(par, md, xo, po, eta, veta, f, 40)
     assert rel_max(xg, xo) <= 1e-9
     assert rel_max(pg, po) <= 1e-9
-    assert rel_max(nhc[1], veta) <= 1e-8
+    assert rel_max(nhc[:-1].reshape(veta.shape), veta) <= 1e-8
+    assert abs(nhc[-1] - float(np.sum(eta))) <= 1e-8 * float(np.sum(np.abs(eta)))
 
 
 def test_conserved_quantity_and_density(orc):
