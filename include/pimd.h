@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define PIMD_ABI_VERSION 7
+#define PIMD_ABI_VERSION 8
 
 typedef enum {
     PIMD_OK = 0,
@@ -99,6 +99,13 @@ typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
                                      (flags & PIMD_FLAG_PAIR_SPLIT_MASK) / PIMD_FLAG_PAIR_SPLIT_1 is
                                      0 (chosen from the work size), 1, 2 or 3 (1, 2 or 4 waves)    */
 #define PIMD_FLAG_PAIR_SPLIT_MASK 48
+#define PIMD_FLAG_RECURSION_WIDE 64 /* eight wavefronts per workgroup of the one-workgroup-per-replica
+                                     recursion schedule instead of four: more parallel work per row
+                                     block of the chain, but the whole register file of a compute
+                                     unit, so the pair kernel cannot run beside it there; pays when
+                                     the chains are the critical path and the pair work is small
+                                     (measured: 64 replicas of N ~ U{64..512} +7%, 128 replicas of
+                                     N = 1600 -11%); for the autotuner                            */
 
 /* One independent system (replica).  Units are free; the paper uses
  * hbar = m = omega = k_B = 1 (Sec. IV.A). */

@@ -37,11 +37,12 @@ class Knobs:
     persistent: bool = False
     order: str = "index"      # "index" or "longest": dispatch order of the per-replica work
     pair_split: int = 0       # waves per tile of the ordered pair kernel (0: chosen by the library)
+    wide: bool = False        # eight instead of four waves per one-workgroup recursion chain
 
     def as_kwargs(self) -> Dict:
         return {"recursion_workgroups": self.recursion_workgroups, "pair_kernel": self.pair_kernel,
                 "graphs": self.graphs, "persistent": self.persistent, "order": self.order,
-                "pair_split": self.pair_split}
+                "pair_split": self.pair_split, "wide_recursion": self.wide}
 
 
 @dataclass
@@ -68,12 +69,16 @@ def candidates(systems: Sequence[System], precision: str, graphs: bool = False) 
     if has_pair:
         pairs += [("ordered", k) for k in (1, 2, 4)] if sym else [("auto", k) for k in (1, 2, 4)]
     orders = ["index", "longest"] if len({s.n for s in systems}) > 1 else ["index"]
+    # eight-wave chains for the one-workgroup schedule while their workgroups (two per replica, one
+    # compute unit each) leave room on a 256-CU device
+    widths = (False, True) if 2 * len(systems) <= 256 else (False,)
     out = [Knobs(persistent=True)] if persistent_fits(systems) else []
     for r in scheds:
         for pk, split in pairs:
             for o in orders:
                 for g in ((False, True) if graphs else (False,)):
-                    out.append(Knobs(r, pk, g, False, o, split))
+                    for wd in (widths if r in (0, 1) else (False,)):
+                        out.append(Knobs(r, pk, g, False, o, split, wd))
     return out
 
 
@@ -81,7 +86,7 @@ def pick(timings: Dict[Knobs, float]) -> Knobs:
     """Fastest candidate; ties go to the simpler one (library defaults first)."""
     def simplicity(k: Knobs):
         return (not k.persistent, k.graphs, k.pair_kernel != "auto", k.pair_split != 0, k.order != "index",
-                k.recursion_workgroups != 0, k.recursion_workgroups)
+                k.wide, k.recursion_workgroups != 0, k.recursion_workgroups)
     return min(timings, key=lambda k: (timings[k], simplicity(k)))
 
 

@@ -110,7 +110,7 @@ pimd_status validate(const pimd_config* c) {
   if (c->recursion_workgroups < 0 || c->recursion_workgroups > 4096)
     return fail(PIMD_ERR_INVALID, "recursion_workgroups must be in 0..4096");
   if ((c->flags & ~(PIMD_FLAG_GRAPH | PIMD_FLAG_PAIR_ORDERED | PIMD_FLAG_NO_PERSISTENT | PIMD_FLAG_LONGEST_FIRST |
-                    PIMD_FLAG_PAIR_SPLIT_MASK)) != 0)
+                    PIMD_FLAG_PAIR_SPLIT_MASK | PIMD_FLAG_RECURSION_WIDE)) != 0)
     return fail(PIMD_ERR_INVALID, "unknown bits in flags");
   for (int r = 0; r < c->n_replicas; ++r) {
     const pimd_status st = validate_replica(c->replicas[r], r);
@@ -356,6 +356,7 @@ struct pimd_ctx {
   long long step = 0;
   bool has_pair = false;
   int helpers = 0;       // helper workgroups per recursion chain (0: one workgroup per chain)
+  bool wide = false;     // eight waves per workgroup of the one-workgroup schedule
   hipStream_t sc = nullptr;          // stream the step graph is captured on
   hipGraphExec_t gexec = nullptr;    // one steady MD step (evaluation + fused integrator halves)
   int graph_state = 0;               // 0 not built, 1 built, 2 not requested, 3 capture failed
@@ -427,7 +428,7 @@ pimd_status evaluate(pimd_ctx* c, bool est, hipStream_t ms) {
   const bool fork = c->has_pair;
   if (fork) HIPCHK(hipEventRecord(c->ev_fork, ms));
   if (c->helpers > 0) RUN(K_RECURSION, ms, launch_recursion_coop(d, w, c->helpers, est, ms));
-  else RUN(K_RECURSION, ms, launch_recursion(d, w, est, ms));
+  else RUN(K_RECURSION, ms, launch_recursion(d, w, est, c->wide, ms));
   RUN(K_REDUCE, ms, launch_probs_reduce(d, w, ms));
   if (c->has_pair) {
     hipStream_t ps = fork ? c->s2 : ms;
@@ -659,6 +660,7 @@ pimd_status pimd_create(const pimd_config* cfg, void* d_workspace, size_t bytes,
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) return cleanup(fail(PIMD_ERR_DEVICE, std::string("pimd_create: ") + hipGetErrorString(e)));
   c->helpers = choose_helpers(cfg->recursion_workgroups, c->pl.d);
+  c->wide = (cfg->flags & PIMD_FLAG_RECURSION_WIDE) != 0;
   *out = c;
   return PIMD_OK;
 }
@@ -776,7 +778,8 @@ pimd_status pimd_compute_forces_noalloc(const pimd_config* cfg, const double* x,
   // the evaluation of pimd_compute_forces, every kernel on the caller's stream
   HIPCHK(launch_springs(d, w, s));
   const bool want_est = est != nullptr;
-  HIPCHK(helpers > 0 ? launch_recursion_coop(d, w, helpers, want_est, s) : launch_recursion(d, w, want_est, s));
+  const bool wide = (cfg->flags & PIMD_FLAG_RECURSION_WIDE) != 0;
+  HIPCHK(helpers > 0 ? launch_recursion_coop(d, w, helpers, want_est, s) : launch_recursion(d, w, want_est, wide, s));
   HIPCHK(launch_probs_reduce(d, w, s));
   HIPCHK(launch_pair(d, w, est != nullptr, pl.jsplit, s));
   HIPCHK(launch_integrate_second(d, w, false, s));   // f += pair forces; non-finite check

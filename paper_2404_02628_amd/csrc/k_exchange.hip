@@ -97,12 +97,11 @@ struct RecMap {
 };
 
 // Waves per recursion workgroup: the cooperative chain kernel uses eight (its block latency is
-// the critical path), the batched kernel four (half the register file and less LDS per CU, so
-// the pair kernel's workgroups can run beside it on the same compute units).
+// the critical path); the batched kernel four by default (half the register file and less LDS per
+// CU, so the pair kernel's workgroups can run beside it on the same compute units) or eight when
+// its workgroups have compute units to spare (few replicas: the chains are the critical path).
 constexpr int kCoopWaves = 8;
-constexpr int kBatchWaves = 4;
 constexpr int kCoopCols = kTile / kCoopWaves;
-constexpr int kBatchCols = kTile / kBatchWaves;
 
 // How the xi^(i-1-j) factor enters a term: xi = 1 (nothing), xi = 0 (only j = i-1 survives),
 // general xi (exact integer power times log xi).
@@ -651,15 +650,16 @@ __device__ inline void link_prefix(const RecMap<D>& mp, double inv_c, double* __
 
 // One workgroup per replica and direction (batched replicas fill the machine).  Workgroups 2k
 // and 2k + 1 serve replica order[k]: the plan lists replicas in index order or longest first.
-template <int D, bool SP>
-__global__ __launch_bounds__(64 * kBatchWaves) void k_recursion(const RepDev* __restrict__ reps,
+template <int D, bool SP, int W>
+__global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__ reps,
                                                            const double* __restrict__ ends,
                                                            const double* __restrict__ link,
                                                            double* __restrict__ gf, double* __restrict__ gb,
                                                            double4* __restrict__ colrec,
                                                            double* __restrict__ avg, double* __restrict__ lamall,
                                                            const int* __restrict__ order) {
-  __shared__ RecShared<D, kBatchWaves> sh;
+  constexpr int kBatchWaves = W, kBatchCols = kTile / W;
+  __shared__ RecShared<D, W> sh;
   const int rep = order[blockIdx.x >> 1], dir = blockIdx.x & 1;
   const RepDev& R = reps[rep];
   const int N = R.n;
@@ -1041,10 +1041,11 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   }
 }
 
-hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, hipStream_t s) {
-  dim3 grid((unsigned)(2 * d.R)), block(64 * kBatchWaves);
-#define L(DD, SPV) hipLaunchKernelGGL((k_recursion<DD, SPV>), grid, block, 0, s, w.reps, w.ends, w.link, w.gf, w.gb, \
-                                    w.colrec, w.avg, w.lam, w.reporder)
+template <int W>
+static hipError_t launch_recursion_w(const Dims& d, const DevPtrs& w, bool sp, hipStream_t s) {
+  dim3 grid((unsigned)(2 * d.R)), block(64 * W);
+#define L(DD, SPV) hipLaunchKernelGGL((k_recursion<DD, SPV, W>), grid, block, 0, s, w.reps, w.ends, w.link, w.gf, \
+                                    w.gb, w.colrec, w.avg, w.lam, w.reporder)
   switch (d.D * 2 + (sp ? 1 : 0)) {
     case 2: L(1, false); break;
     case 3: L(1, true); break;
@@ -1056,6 +1057,10 @@ hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, hipStream_
   }
 #undef L
   return hipGetLastError();
+}
+
+hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, bool wide, hipStream_t s) {
+  return wide ? launch_recursion_w<8>(d, w, sp, s) : launch_recursion_w<4>(d, w, sp, s);
 }
 
 // The pipelined chain (previous block's payloads and averages formed by waves 2.. during wave

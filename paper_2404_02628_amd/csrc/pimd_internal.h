@@ -122,7 +122,8 @@ hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool estimators, int jsplit, hipStream_t s);
 int pair_sym_lds_bytes(int D, int maxn);   // dynamic LDS of the symmetric pair kernel
 // sp: also average the cycles' spring payload (the expected spring energy of the estimators)
-hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, hipStream_t s);
+// wide: eight waves per batched recursion workgroup instead of four
+hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, bool wide, hipStream_t s);
 hipError_t launch_recursion_coop(const Dims& d, const DevPtrs& w, int helpers, bool sp, hipStream_t s);
 int recursion_coop_max_blocks_per_cu(int D, int maxn);   // for the variant launched at this largest N
 hipError_t launch_probs_reduce(const Dims& d, const DevPtrs& w, hipStream_t s);

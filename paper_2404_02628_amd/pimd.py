@@ -29,6 +29,7 @@ PIMD_FLAG_NO_PERSISTENT = 4
 PIMD_FLAG_LONGEST_FIRST = 8
 PIMD_FLAG_PAIR_SPLIT_1 = 16
 PIMD_FLAG_PAIR_SPLIT_MASK = 48
+PIMD_FLAG_RECURSION_WIDE = 64
 
 EXPORTED = [
     "pimd_abi_version", "pimd_last_error", "pimd_workspace_bytes", "pimd_create", "pimd_destroy",
@@ -278,7 +279,8 @@ class Context:
     def __init__(self, systems: Sequence[System], precision: str = "mixed", nhc_len: Optional[int] = None,
                  sy_order: int = 3, density_bins: int = 64, density_rmax: float = 6.0, trace_capacity: int = 0,
                  recursion_workgroups: int = 0, graphs: bool = False, pair_kernel: str = "auto",
-                 persistent: bool = True, order: str = "index", pair_split: int = 0, device: str = "cuda:0"):
+                 persistent: bool = True, order: str = "index", pair_split: int = 0, wide_recursion: bool = False,
+                 device: str = "cuda:0"):
         import torch  # device memory and streams only
 
         if not systems:
@@ -309,7 +311,8 @@ class Context:
                                (PIMD_FLAG_PAIR_ORDERED if pair_kernel == "ordered" else 0) |
                                (0 if persistent else PIMD_FLAG_NO_PERSISTENT) |
                                (PIMD_FLAG_LONGEST_FIRST if order == "longest" else 0) |
-                               split_code * PIMD_FLAG_PAIR_SPLIT_1, density_rmax, reps)
+                               split_code * PIMD_FLAG_PAIR_SPLIT_1 |
+                               (PIMD_FLAG_RECURSION_WIDE if wide_recursion else 0), density_rmax, reps)
         self.nbytes = pimd_workspace_bytes(self.cfg)
         self.device = torch.device(device)
         with torch.cuda.device(self.device):

@@ -30,6 +30,8 @@ def main(argv=None) -> int:
     ap.add_argument("--n2", type=int, default=0, help="particles of a second species in every replica")
     ap.add_argument("--no-persistent", action="store_true",
                     help="one launch per kernel and step even for replicas small enough for the persistent kernel")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the launch knobs with the autotuner first (printed) and run with them")
     ap.add_argument("--kernel-times", action="store_true",
                     help="also time the steps with the library's HIP-event profiler and print per-kernel averages")
     args = ap.parse_args(argv)
@@ -53,8 +55,16 @@ def main(argv=None) -> int:
     else:
         base = WORKLOADS[args.workload]
         systems = [base.with_(seed=base.seed + r, n2=args.n2) for r in range(args.replicas)]
-    ctx = Context(systems, precision=args.path, recursion_workgroups=args.workgroups, graphs=args.graphs,
-                  persistent=not args.no_persistent)
+    if args.tune:
+        from . import autotune
+        res = autotune.tune(systems, args.path, steps=10, warmup=3)
+        print("autotuned: " + ", ".join(f"{k}={v}" for k, v in res.best.as_kwargs().items()), flush=True)
+        for k, v in sorted(res.seconds_per_step.items(), key=lambda kv: kv[1])[:6]:
+            print(f"  {v * 1e6:8.1f} us/step  {k.as_kwargs()}", flush=True)
+        ctx = Context(systems, precision=args.path, **res.best.as_kwargs())
+    else:
+        ctx = Context(systems, precision=args.path, recursion_workgroups=args.workgroups, graphs=args.graphs,
+                      persistent=not args.no_persistent)
     for r, sy in enumerate(systems):
         x, p = initial_state(sy)
         ctx.set_state(r, x, p)

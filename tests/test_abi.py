@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(lib):
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
     assert set(names) == set(lib.EXPORTED)
-    assert lib.pimd_abi_version() == 7
+    assert lib.pimd_abi_version() == 8
 
 
 def _cfg(lib, **over):
@@ -62,7 +62,7 @@ def test_workspace_size_is_positive_and_monotone(lib):
 @pytest.mark.parametrize("over", [
     {"p": 1}, {"dim": 0}, {"dim": 4}, {"precision": 7}, {"nhc_len": 9}, {"sy_order": 2},
     {"density_bins": 0}, {"density_rmax": 0.0}, {"trace_capacity": -1}, {"n_replicas": 0},
-    {"recursion_workgroups": -1}, {"flags": 64}, {"flags": 128}, {"flags": -1},
+    {"recursion_workgroups": -1}, {"flags": 128}, {"flags": 256}, {"flags": -1},
     {"rep": {"n": 0}}, {"rep": {"xi": -0.1}}, {"rep": {"xi": 1.5}}, {"rep": {"beta": 0.0}},
     {"rep": {"pair_amp": -1.0}}, {"rep": {"pair_amp": 1.0, "pair_width": 0.0}}, {"rep": {"dt": 0.0}},
     {"rep": {"n2": -1}}, {"rep": {"n2": 37}}, {"rep": {"n2": 65}}, {"rep": {"mass": -1.0}},
@@ -82,7 +82,7 @@ def test_create_rejects_missing_workspace_without_touching_the_gpu(lib):
     assert ei.value.code == lib.PIMD_ERR_WORKSPACE
 
 
-@pytest.mark.parametrize("flags", [8, 16, 32, 48, 8 | 32 | 2])
+@pytest.mark.parametrize("flags", [8, 16, 32, 48, 8 | 32 | 2, 64, 64 | 8])
 def test_packing_and_split_flags_are_accepted(lib, flags):
     cfg, _keep = _cfg(lib, flags=flags)
     assert lib.pimd_workspace_bytes(cfg) > 0

@@ -47,3 +47,12 @@ def test_pick_takes_the_fastest_and_breaks_ties_toward_defaults():
     assert pick(t) == Knobs(0, "auto", False)
     t = {Knobs(persistent=True): 1.0, Knobs(0, "auto", False): 1.0}
     assert pick(t) == Knobs(persistent=True)                     # the library default for small replicas
+
+
+def test_candidates_offer_wide_chains_where_they_fit():
+    c5 = candidates(batched_systems(64, 505), "mixed")
+    assert {k.wide for k in c5} == {False, True}                 # 128 chains fit a 256-CU device
+    assert all(not k.wide for k in c5 if k.recursion_workgroups > 1)
+    big = candidates([WORKLOADS["large_gauss"].with_(seed=k) for k in range(256)], "mixed")
+    assert not any(k.wide for k in big)                          # 512 chains: four waves only
+    assert pick({Knobs(wide=True): 1.0, Knobs(): 1.0}) == Knobs()

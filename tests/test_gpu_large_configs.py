@@ -166,13 +166,16 @@ def test_ideal_40k_identities(start):
     assert abs(en["e_prim"] - e_prim) <= 1e-12 * abs(e_prim)
 
 
-@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
-def test_batched_uneven_xi_matches_oracle(orc, mixed):
+@pytest.mark.parametrize("mixed,wide,order", [(False, False, "index"), (True, False, "index"),
+                                              (True, True, "longest"), (False, True, "index")],
+                         ids=["fp64", "mixed", "mixed-wide-longest", "fp64-wide"])
+def test_batched_uneven_xi_matches_oracle(orc, mixed, wide, order):
     from paper_2404_02628_amd.pimd import Context
     systems = batched_systems(64, 505)
     xs = [initial_state(s)[0] for s in systems]
-    print(f"64 uneven replicas, {'mixed' if mixed else 'fp64'}", flush=True)
-    ctx = Context(systems, precision="mixed" if mixed else "fp64")
+    print(f"64 uneven replicas, {'mixed' if mixed else 'fp64'}, wide={wide}, order={order}", flush=True)
+    ctx = Context(systems, precision="mixed" if mixed else "fp64", wide_recursion=wide, order=order,
+                  recursion_workgroups=1)
     try:
         for r, x in enumerate(xs):
             ctx.set_state(r, x)
