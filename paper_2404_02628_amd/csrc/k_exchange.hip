@@ -240,6 +240,28 @@ __device__ inline void bulk_rows(const RowCtx& rc, const double (&pi)[D], double
   if (__any(bad)) bulk_online<D, XM, SP>(rc, pi, rec, lam, ja, jb, tab, m, s, P);
 }
 
+// Step (0) of a block for one wave: the largest term over its NC columns j0.. of the previous
+// block (records cp, in LDS), columns below jlo excluded.  All records are read before the first
+// term, so the reads overlap instead of each waiting out its own latency.
+template <int D, int XM, int NC>
+__device__ inline double ref_max(const RowCtx& rc, const double (&pi)[D], const double4* cp, int j0, int jlo) {
+  double mx = -INFINITY;
+  constexpr int kHalf = NC > 8 ? 8 : (NC > 4 ? 4 : NC);
+#pragma unroll
+  for (int u0 = 0; u0 < NC; u0 += kHalf) {
+    double4 r4[kHalf];
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u) r4[u] = cp[u0 + u];
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u) {
+      double d2;
+      const double t = term_of<D, XM>(rc, pi, r4[u], j0 + u0 + u, d2);
+      mx = (j0 + u0 + u < jlo) ? mx : fmax(mx, t);
+    }
+  }
+  return mx;
+}
+
 template <int D, int XM>
 __device__ inline double max_term(const RowCtx& rc, const double (&pi)[D], const double4* __restrict__ rec, int j0,
                                   int n) {
@@ -251,11 +273,13 @@ __device__ inline double max_term(const RowCtx& rc, const double (&pi)[D], const
   return mx;
 }
 
-// LDS of one recursion workgroup.
-template <int D, int W>
+// LDS of one recursion workgroup; NR > 0 also keeps the column records of the first NR columns
+// (every column of a replica with N <= NR), which the earlier-column sums then read from LDS.
+template <int D, int W, int NR = 0>
 struct RecShared {
   static constexpr int kWaves = W;
   static constexpr int kCols = kTile / W;   // in-block columns per wave
+  static constexpr int kLdsRecs = NR;
   double tab[kExpTable];
   double Am[kTile * kTile];             // in-block coefficients, column-major: Am[col * 64 + row]
   double pm[W][kTile], ps[W][kTile];
@@ -263,6 +287,7 @@ struct RecShared {
   double qp[W][D + 1][kTile];   // per-wave weighted payloads of the in-block columns
   double Dl[kTile], Wl[kTile];          // row scales D_i and scaled unknowns w_i of the block
   double4 col[2][kTile];                // column records {q_j, gamma_j (+ G_j once solved)}: this block, previous
+  double4 recs[NR > 0 ? NR : 1];        // completed column records 0..NR-1 (NR > 0)
 };
 
 // What wave 0 keeps in registers from a block's solve until it writes the block's row averages
@@ -420,6 +445,9 @@ __device__ inline void finish_rows(SH& sh, int blk, int cur, int N, bool valid, 
       r4.w += Gi;
       sh.col[cur][lane] = r4;
       rec[i] = r4;
+      if constexpr (SH::kLdsRecs > 0) {
+        if (i < SH::kLdsRecs) sh.recs[i] = r4;
+      }
     }
   }
   sh.col[cur ^ 1][lane] = col_next;
@@ -601,6 +629,12 @@ __device__ inline RecMap<D> rec_map(const RepDev& R, const double* ends, const d
 
 __device__ inline int xi_mode(double xi) { return xi == 1.0 ? kXiOne : (xi == 0.0 ? kXiZero : kXiGen); }
 
+// Waits until this wave's vector memory operations have completed.  The block loops call it
+// after the next block's prefetch has been consumed or is due, before the block's global stores:
+// the loop head then finds the prefetched registers complete on every path and needs no wait,
+// where it would otherwise wait for those stores too (vector memory operations complete in order).
+__device__ inline void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
 // Register-prefetched inputs of the next block: end points and link values of its rows (all
 // waves), raw column points of its columns (wave 0).
 template <int D>
@@ -619,10 +653,12 @@ struct Prefetch {
 
 // lam_j = (1/c) sum_{m<j} link_m for the columns j = 0..N-1 of the forward recursion (zeros for the
 // backward one, whose averages of this payload are not used), written by the whole workgroup
-// before its first block; lds holds one double per wave.  The fence makes the values visible to
-// the other workgroups of a cooperative launch before any panel is published.
+// before its first block; lds holds one double per wave.  With `device_fence` the values are made
+// visible to the other workgroups of a cooperative launch before any panel is published; a
+// workgroup that reads them itself only needs its barrier.
 template <int D>
-__device__ inline void link_prefix(const RecMap<D>& mp, double inv_c, double* __restrict__ lam, double* lds) {
+__device__ inline void link_prefix(const RecMap<D>& mp, double inv_c, double* __restrict__ lam, double* lds,
+                                   bool device_fence) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double carry = 0.0;
   for (int base = 0; base < mp.N; base += blockDim.x) {
@@ -644,13 +680,19 @@ __device__ inline void link_prefix(const RecMap<D>& mp, double inv_c, double* __
     carry = tot;
     __syncthreads();
   }
-  __threadfence();
+  if (device_fence) __threadfence();
   __syncthreads();
 }
 
+// Columns whose records the batched recursion keeps in LDS when every replica has N <= this: the
+// earlier-column sums of small replicas (whose chains are the critical path of a step) then read
+// their records at LDS latency instead of L2 latency.
+constexpr int kLdsRecCap = 1024;
+
 // One workgroup per replica and direction (batched replicas fill the machine).  Workgroups 2k
 // and 2k + 1 serve replica order[k]: the plan lists replicas in index order or longest first.
-template <int D, bool SP, int W>
+// LR: column records read from LDS (every N <= kLdsRecCap).
+template <int D, bool SP, int W, bool LR>
 __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__ reps,
                                                            const double* __restrict__ ends,
                                                            const double* __restrict__ link,
@@ -659,13 +701,16 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
                                                            double* __restrict__ avg, double* __restrict__ lamall,
                                                            const int* __restrict__ order) {
   constexpr int kBatchWaves = W, kBatchCols = kTile / W;
-  __shared__ RecShared<D, W> sh;
+  __shared__ RecShared<D, W, LR ? kLdsRecCap : 0> sh;
   const int rep = order[blockIdx.x >> 1], dir = blockIdx.x & 1;
   const RepDev& R = reps[rep];
   const int N = R.n;
   const RecMap<D> mp = rec_map<D>(R, ends, link, dir);
   double* G = (dir == 0 ? gf : gb) + R.part;
   double4* rec = colrec + 2LL * R.part + (long long)dir * R.npp;
+  const double4* recs;   // where the earlier-column sums read the records
+  if constexpr (LR) recs = sh.recs;
+  else recs = rec;
   double* av = avg + 2LL * (D + 1) * R.part + (long long)dir * (D + 1) * R.npp;
   double* lam = lamall + 2LL * R.part + (long long)dir * R.npp;
   const double bc = R.beta * R.c, lnxi = R.lnxi;
@@ -675,11 +720,12 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
   const long long npp = R.npp;
 
   if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
-  link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0]);
+  link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0], false);
   Prefetch<D> pf;
   pf.load(mp, 0, wave == 0);
   if (wave == 0) sh.col[0][lane] = make_col<D>(mp, lane, pf.q);
   RowCarry<D> cy{};
+  vm_drain();
   __syncthreads();
 
   for (int blk = 0; blk < nblk; ++blk) {
@@ -704,20 +750,11 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
     if (jend > 0) {
       double mx = -INFINITY;
       if (bulk_ok) {
-        const double4* cp = sh.col[cur ^ 1];
-        const int j0 = wave * kBatchCols;
-#pragma unroll
-        for (int u = 0; u < kBatchCols; ++u) {
-          double d2;
-          const double4 r4 = cp[j0 + u];
-          const int j = jend - kTile + j0 + u;
-          double t;
-          if (xm == kXiOne) t = term_of<D, kXiOne>(rc, pi, r4, j, d2);
-          else if (xm == kXiZero) t = term_of<D, kXiZero>(rc, pi, r4, j, d2);
-          else t = term_of<D, kXiGen>(rc, pi, r4, j, d2);
-          if (j < jlo) t = -INFINITY;
-          mx = fmax(mx, t);
-        }
+        const double4* cp = sh.col[cur ^ 1] + wave * kBatchCols;
+        const int j0 = jend - kTile + wave * kBatchCols;
+        if (xm == kXiOne) mx = ref_max<D, kXiOne, kBatchCols>(rc, pi, cp, j0, jlo);
+        else if (xm == kXiZero) mx = ref_max<D, kXiZero, kBatchCols>(rc, pi, cp, j0, jlo);
+        else mx = ref_max<D, kXiGen, kBatchCols>(rc, pi, cp, j0, jlo);
       }
       sh.pm[wave][lane] = mx;
       __syncthreads();
@@ -735,9 +772,9 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
     if (bulk_ok && jend > jlo) {
       const int per = (jend - jlo + kBatchWaves - 1) / kBatchWaves;
       const int ja = min(jend, jlo + wave * per), jb = min(jend, ja + per);
-      if (xm == kXiOne) bulk_rows<D, kXiOne, SP>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
-      else if (xm == kXiZero) bulk_rows<D, kXiZero, SP>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
-      else bulk_rows<D, kXiGen, SP>(rc, pi, Rref, rec, lam, ja, jb, sh.tab, m, s, P);
+      if (xm == kXiOne) bulk_rows<D, kXiOne, SP>(rc, pi, Rref, recs, lam, ja, jb, sh.tab, m, s, P);
+      else if (xm == kXiZero) bulk_rows<D, kXiZero, SP>(rc, pi, Rref, recs, lam, ja, jb, sh.tab, m, s, P);
+      else bulk_rows<D, kXiGen, SP>(rc, pi, Rref, recs, lam, ja, jb, sh.tab, m, s, P);
     }
     sh.pm[wave][lane] = m;
     sh.ps[wave][lane] = s;
@@ -745,6 +782,7 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
     for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = P[q];
     inblock_alpha<D>(sh, sh.Am, cur, blk, i, pi, rho, valid, bc, lnxi, mp.bnd);
     const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
+    vm_drain();
     solve_block<D, false, SP>(sh, sh.Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, nullptr, 0, cy, [] {},
                           sh.Am, [](double (&)[D], double&) {}, nullptr);
   }
@@ -864,7 +902,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
 
   if (is_chain) {
-    link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0]);   // before panel 0 is published
+    link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0], true);   // before panel 0 is published
     Prefetch<D> pf;
     pf.load(mp, 0, wave == 0);
     if (wave == 0) sh.col[0][lane] = make_col<D>(mp, lane, pf.q);
@@ -887,6 +925,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
     double hm = -1e300, hs = 0.0, hP[D + 1];
 #pragma unroll
     for (int q = 0; q <= D; ++q) hP[q] = 0.0;
+    vm_drain();
     __syncthreads();
     for (int blk = 0; blk < nblk; ++blk) {
       const int cur = blk & 1;
@@ -929,6 +968,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
 #pragma unroll
       for (int q = 0; q <= D; ++q) sh.pp[wave][q][lane] = P[q];
       const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
+      vm_drain();
       const int nb = blk + 1;
       auto fetch_next = [&] {
         have_part = false;
@@ -1041,11 +1081,11 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   }
 }
 
-template <int W>
+template <int W, bool LR>
 static hipError_t launch_recursion_w(const Dims& d, const DevPtrs& w, bool sp, hipStream_t s) {
   dim3 grid((unsigned)(2 * d.R)), block(64 * W);
-#define L(DD, SPV) hipLaunchKernelGGL((k_recursion<DD, SPV, W>), grid, block, 0, s, w.reps, w.ends, w.link, w.gf, \
-                                    w.gb, w.colrec, w.avg, w.lam, w.reporder)
+#define L(DD, SPV) hipLaunchKernelGGL((k_recursion<DD, SPV, W, LR>), grid, block, 0, s, w.reps, w.ends, w.link, \
+                                    w.gf, w.gb, w.colrec, w.avg, w.lam, w.reporder)
   switch (d.D * 2 + (sp ? 1 : 0)) {
     case 2: L(1, false); break;
     case 3: L(1, true); break;
@@ -1060,7 +1100,9 @@ static hipError_t launch_recursion_w(const Dims& d, const DevPtrs& w, bool sp, h
 }
 
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, bool wide, hipStream_t s) {
-  return wide ? launch_recursion_w<8>(d, w, sp, s) : launch_recursion_w<4>(d, w, sp, s);
+  if (d.maxn <= kLdsRecCap)
+    return wide ? launch_recursion_w<8, true>(d, w, sp, s) : launch_recursion_w<4, true>(d, w, sp, s);
+  return wide ? launch_recursion_w<8, false>(d, w, sp, s) : launch_recursion_w<4, false>(d, w, sp, s);
 }
 
 // The pipelined chain (previous block's payloads and averages formed by waves 2.. during wave
