@@ -41,6 +41,14 @@
 // beta sum link, so a small Pr[l -> l+1] carries an absolute error of their rounding; the forces
 // take it at that absolute size, while S never multiplies it by a link energy.)
 //
+// Expanded terms.  For d <= 2 a completed column record also holds, in its third slot, the column
+// constant B_j = gamma_j + G_j - beta c |q_j|^2 - j log xi (log xi taken as 0 for xi = 1 and
+// for xi = 0, whose terms are formed directly), so that the earlier-column sums form a term as
+// A_i + B_j + 2 beta c p_i.q_j with the row constant A_i = rho_i - beta c |p_i|^2 + (i-1) log xi:
+// three operations instead of six (the xi power costs nothing).  The expansion rounds at the
+// size of beta c (|p_i|^2 + |q_j|^2) instead of beta c |p_i - q_j|^2, an absolute error of a few
+// 1e-13 in the exponent for the trapped systems here, far below the parity bounds.
+//
 // Recursion schedule (one workgroup per replica and direction, four wavefronts).  Rows are
 // processed in blocks of 64 (lane = row).  For a block: (0) a reference R_i = the largest term of
 // the previous block's columns (a lower bound of the row's largest earlier term); (1) the four
@@ -139,6 +147,19 @@ template <int D, int XM, bool SP>
 __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], double R, const double4* __restrict__ rec,
                                   const double* __restrict__ lam, int ja, int jb, const double* tab, double& s_out,
                                   double (&P)[D + 1]) {
+  // expanded terms (records carry B_j) unless the spring payload needs |p_i - q_j|^2 itself
+  constexpr bool kExpand = D <= 2 && XM != kXiZero && !SP;
+  double P2[D], Arow = 0.0;   // 2 beta c p_i and A_i - R
+  if constexpr (kExpand) {
+    double p2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      P2[c] = 2.0 * rc.bc * pi[c];
+      p2 = fma(pi[c], pi[c], p2);
+    }
+    Arow = fma(-rc.bc, p2, rc.rowc - R);
+    if constexpr (XM == kXiGen) Arow = fma((double)(rc.i - 1), rc.lnxi, Arow);
+  }
   double s[2] = {0.0, 0.0}, pq[2][D + 1];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -158,8 +179,15 @@ __device__ inline void bulk_fixed(const RowCtx& rc, const double (&pi)[D], doubl
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = j0 + u;
-      double d2;
-      double t = term_of<D, XM>(rr, pi, g[u], j, d2);   // t_{i,j} - R
+      double d2 = 0.0, t;   // t_{i,j} - R
+      if constexpr (kExpand) {
+        const double qv[3] = {g[u].x, g[u].y, g[u].z};
+        t = Arow + g[u].z;
+#pragma unroll
+        for (int c = 0; c < D; ++c) t = fma(P2[c], qv[c], t);
+      } else {
+        t = term_of<D, XM>(rr, pi, g[u], j, d2);
+      }
       if constexpr (decltype(masked)::value) {
         if (j >= jb) t = -INFINITY;
       }
@@ -430,10 +458,14 @@ __device__ inline void scaled_coefficients(SH& sh, double* __restrict__ Am) {
 
 // G_i, the completed column record of row i (LDS and global), the next block's column records,
 // the publish store and the carried row data; wave 0 only.
+// Column constants of the expanded terms: beta c and the log xi that they fold in.
+struct ColConst { double bc, lnxf; };
+
 template <int D, class SH>
 __device__ inline void finish_rows(SH& sh, int blk, int cur, int N, bool valid, double Di, double wi,
                                    double bterm, double4* __restrict__ rec, double* __restrict__ G,
-                                   const double4& col_next, int* publish, int epoch, RowCarry<D>& cy) {
+                                   const double4& col_next, int* publish, int epoch, RowCarry<D>& cy,
+                                   const ColConst& cc) {
   const int lane = threadIdx.x & 63;
   const int i = blk * kTile + lane;
   sh.Wl[lane] = wi;
@@ -443,6 +475,11 @@ __device__ inline void finish_rows(SH& sh, int blk, int cur, int N, bool valid, 
     if (i < N) {
       double4 r4 = sh.col[cur][lane];
       r4.w += Gi;
+      if constexpr (D <= 2) {   // B_i of the expanded terms
+        double q2 = r4.x * r4.x;
+        if (D > 1) q2 = fma(r4.y, r4.y, q2);
+        r4.z = fma(-(double)i, cc.lnxf, fma(-cc.bc, q2, r4.w));
+      }
       sh.col[cur][lane] = r4;
       rec[i] = r4;
       if constexpr (SH::kLdsRecs > 0) {
@@ -542,7 +579,7 @@ __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int
                                    long long npp, const double (&pi)[D], double lrow, const double* __restrict__ lam,
                                    const double4& col_next, int* publish,
                                    int epoch, RowCarry<D>& cy, Idle&& idle, const double* __restrict__ Am_prev,
-                                   PrevRows&& prev_rows, PipeRows<D>* prow) {
+                                   PrevRows&& prev_rows, PipeRows<D>* prow, const ColConst& cc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = blk * kTile + lane;
   __syncthreads();
@@ -583,7 +620,7 @@ __device__ inline void solve_block(SH& sh, double* __restrict__ Am, int blk, int
     const double Di = sh.Dl[lane];
     const double bterm = fast_exp(LB - Di, sh.tab);
     const double wi = substitute_regs(Am, bterm);
-    finish_rows<D>(sh, blk, cur, N, valid, Di, wi, bterm, rec, G, col_next, publish, epoch, cy);
+    finish_rows<D>(sh, blk, cur, N, valid, Di, wi, bterm, rec, G, col_next, publish, epoch, cy, cc);
     if (PIPE) {
       const int slot = blk & 1;
       prow->w[slot][lane] = wi;
@@ -715,6 +752,7 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
   double* lam = lamall + 2LL * R.part + (long long)dir * R.npp;
   const double bc = R.beta * R.c, lnxi = R.lnxi;
   const int xm = xi_mode(R.xi);
+  const ColConst cc{bc, xm == kXiGen ? lnxi : 0.0};
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (N + 1 + kTile - 1) / kTile;   // rows 0..N
   const long long npp = R.npp;
@@ -784,7 +822,7 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
     const double4 cn = wave == 0 ? make_col<D>(mp, i + kTile, pf.q) : make_double4(0.0, 0.0, 0.0, 0.0);
     vm_drain();
     solve_block<D, false, SP>(sh, sh.Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, nullptr, 0, cy, [] {},
-                          sh.Am, [](double (&)[D], double&) {}, nullptr);
+                          sh.Am, [](double (&)[D], double&) {}, nullptr, cc);
   }
   __syncthreads();
   if (wave == 0) write_avg<D>(sh, cy, av, npp);
@@ -896,6 +934,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   double* pt = partial + 2LL * (D + 3) * R.part + (long long)dir * (D + 3) * R.npp;  // [D+3][npp]: m, s, P
   const double bc = R.beta * R.c, lnxi = R.lnxi;
   const int xm = xi_mode(R.xi);
+  const ColConst cc{bc, xm == kXiGen ? lnxi : 0.0};
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (N + 1 + kTile - 1) / kTile;
   const long long npp = R.npp;
@@ -988,7 +1027,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
       };
       solve_block<D, PIPE, SP>(sh, Am, blk, cur, N, valid, rec, G, av, npp, pi, lrow, lam, cn, panel_ready + blk, epoch,
                            cy, fetch_next, Am_prev, [&](double (&pp)[D], double& lr) { rows_of(blk - 1, pp, lr); },
-                           &prow);
+                           &prow, cc);
     }
     // the last block's payloads (pipelined) and row averages
     __syncthreads();

@@ -21,8 +21,16 @@
 //            This is the least a sequential exchange recursion (Eqs. 6, 11) must spend per row
 //            if everything but the newest term is summed off the chain: the model against
 //            which the recursion kernels' time per row is read.
+//   f64:*    FP64 instruction costs, each measured as that instruction plus one FP64 multiply
+//            per chain step (the multiply keeps the chain's value in range), so the
+//            instruction's own cost is the kind's figure minus `f64:mul`:
+//            fma, mul, add, max, ldexp, rndne, cvt (double -> int -> double counts two)
+//   exp64:*  the FP64 exponential's throughput per call: `table` the library's table-driven
+//            exp (fast_exp.h); `shift` the same with the rounding to an integer done by adding
+//            and subtracting 1.5 * 2^52 (no rndne, no conversion; the integer is the low word)
 // The results decide the pair kernel's design: whether a Gram-matrix formulation on the matrix
-// cores (|r_i - r_j|^2 = |r_i|^2 + |r_j|^2 - 2 r_i.r_j) can beat the plain vector form.
+// cores (|r_i - r_j|^2 = |r_i|^2 + |r_j|^2 - 2 r_i.r_j) can beat the plain vector form; and the
+// FP64 exponential's form in the exchange sums and the FP64 pair kernel.
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstdlib>
@@ -133,6 +141,56 @@ __global__ __launch_bounds__(kThreads) void k_pair(float* out, int iters) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+enum F64Kind { kF64Fma, kF64Mul, kF64Add, kF64Max, kF64Ldexp, kF64Rndne, kF64Cvt, kExpTable64, kExpShift64 };
+
+// the table exponential with the magic-number rounding: kd_s = x 64/ln2 + 1.5 * 2^52 rounds to an
+// integer k held in the low word of kd_s (|k| < 2^31 for x in [-800, 709.8])
+__device__ inline double exp_shift(double x, const double* tab) {
+  const double kInvL = 92.33248261689366, kShift = 6755399441055744.0;   // 64/ln2, 1.5 * 2^52
+  const double kL1 = 0x1.62e42fee00000p-7, kL2 = 0x1.a39ef35793c76p-39;
+  const double xc = fmin(fmax(x, -800.0), 709.8);
+  const double kds = fma(xc, kInvL, kShift);
+  const int k = (int)(unsigned)__double_as_longlong(kds);
+  const double kd = kds - kShift;
+  double r = fma(-kd, kL1, xc);
+  r = fma(-kd, kL2, r);
+  double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = q * r * r + r;
+  const double t = tab[k & 63];
+  return ldexp(fma(t, q, t), k >> 6);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads) void k_f64(float* out, int iters) {
+  __shared__ double tab[pimd::kExpTable];
+  if (threadIdx.x < pimd::kExpTable) tab[threadIdx.x] = pimd::exp_table_entry(threadIdx.x);
+  __syncthreads();
+  double v[8];
+  for (int q = 0; q < 8; ++q) v[q] = 0.5 + 0.01 * q + threadIdx.x * 1e-5;
+  const int e = (int)(blockIdx.x >> 20);   // 0 at run time, unknown to the compiler
+  const double c = 0.25 + e;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double w = v[q];
+      if (KIND == kF64Fma) w = fma(w, 0.999, 1e-4);
+      if (KIND == kF64Add) w = w + c;
+      if (KIND == kF64Max) w = fmax(w, c);
+      if (KIND == kF64Ldexp) w = ldexp(w, e);
+      if (KIND == kF64Rndne) w = rint(w);
+      if (KIND == kF64Cvt) w = (double)(int)w + c;
+      if (KIND == kExpTable64) w = pimd::fast_exp_finite(-w, tab) + c;
+      if (KIND == kExpShift64) w = exp_shift(-w, tab) + c;
+      v[q] = w * 0.9999;   // the multiply every kind carries (f64:mul alone is just this)
+    }
+  }
+  double s = 0.0;
+  for (int q = 0; q < 8; ++q) s += v[q];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = (float)s;
+}
+
 __global__ __launch_bounds__(256) void k_copy(const double2* __restrict__ x, double2* __restrict__ y, long long n2) {
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n2; i += (long long)gridDim.x * 256) y[i] = x[i];
 }
@@ -235,6 +293,23 @@ int main() {
   std::printf("mix     %8.3f ms  %6.2f cycles per iteration (4 mfma4 + 8 exp)\n", ms, cycles(ms, 1));
   ms = time_ms(k_pair, out, iters);
   std::printf("pair    %8.3f ms  %6.2f cycles per 64 pairs (one wave step)\n", ms, cycles(ms, 8));
+  {
+    const int it64 = iters / 4;
+    auto f64 = [&](const char* name, auto kern) {
+      const double m = time_ms(kern, out, it64);
+      std::printf("%-12s %8.3f ms  %6.2f cycles per wave step\n", name, m,
+                  m * 1e-3 * hz * simds / (waves * it64 * 8.0));
+    };
+    f64("f64:mul", k_f64<kF64Mul>);
+    f64("f64:fma", k_f64<kF64Fma>);
+    f64("f64:add", k_f64<kF64Add>);
+    f64("f64:max", k_f64<kF64Max>);
+    f64("f64:ldexp", k_f64<kF64Ldexp>);
+    f64("f64:rndne", k_f64<kF64Rndne>);
+    f64("f64:cvt", k_f64<kF64Cvt>);
+    f64("exp64:table", k_f64<kExpTable64>);
+    f64("exp64:shift", k_f64<kExpShift64>);
+  }
   CK(hipFree(out));
 
   {
