@@ -1,17 +1,17 @@
 // fast_exp.h -- table-driven double-precision exponential for the FP64 kernels.
 //
 // Method: P. T. P. Tang, "Table-driven implementation of the exponential function in IEEE
-// floating-point arithmetic", ACM TOMS 15 (1989) 144.  Write x = (64 m + j) ln2/64 + r with
-// integers m, j in [0, 63] and |r| <= ln2/128; then e^x = 2^m * 2^(j/64) * e^r.  2^(j/64) comes
-// from a 64-entry table (built once per workgroup in LDS), e^r - 1 from its Taylor polynomial
-// of degree 5 (truncation below 4e-17 for |r| <= 0.0055), and 2^m from ldexp, which also
-// produces the gradual underflow to 0 for very negative x.  ln2/64 is split into a 32-bit
+// floating-point arithmetic", ACM TOMS 15 (1989) 144.  Write x = (256 m + j) ln2/256 + r with
+// integers m, j in [0, 255] and |r| <= ln2/512; then e^x = 2^m * 2^(j/256) * e^r.  2^(j/256)
+// comes from a 256-entry table (2 KiB, built once per workgroup in LDS), e^r - 1 from its Taylor
+// polynomial of degree 4 (truncation below 4e-17 for |r| <= 0.00136), and 2^m from ldexp, which
+// also produces the gradual underflow to 0 for very negative x.  ln2/256 is split into a 32-bit
 // high part (k * hi is exact for |k| < 2^21) and a low correction:
-//   64/ln2 = 92.33248261689366, hi = 0x1.62e42fee00000p-7, lo = 0x1.a39ef35793c76p-39.
-// The integer k nearest to x 64/ln2 comes from one fused multiply-add with 1.5 * 2^52, whose
+//   256/ln2 = 369.3299304675746, hi = 0x1.62e42fee00000p-9, lo = 0x1.a39ef35793c76p-41.
+// The integer k nearest to x 256/ln2 comes from one fused multiply-add with 1.5 * 2^52, whose
 // result has unit spacing, so the sum is rounded to an integer and k sits in its low word (valid
-// for |k| < 2^31; here |k| < 2^17): one operation fewer than rounding and converting.
-// About 16 vector instructions instead of ~26 for the library exp; results are within a few
+// for |k| < 2^31; here |k| < 2^19): one operation fewer than rounding and converting.
+// About 15 vector instructions instead of ~26 for the library exp; results are within a few
 // ulp, far below the 1e-10 parity bar.  The function has no branches, so the compiler can
 // interleave independent calls instead of running each one's exec-masked regions in turn: the
 // argument is clamped to [-800, 709.8], where ldexp itself produces the limits (exactly 0 below
@@ -21,18 +21,23 @@
 
 namespace pimd {
 
-constexpr int kExpTable = 64;
+constexpr int kExpTable = 256;
 
-// Fills tab[0..63] with 2^(j/64); call from one workgroup before __syncthreads().
-__host__ __device__ inline double exp_table_entry(int j) { return exp2((double)j / 64.0); }
+__host__ __device__ inline double exp_table_entry(int j) { return exp2((double)j / kExpTable); }
+
+// Fills tab[0..kExpTable-1] with 2^(j/256) using every thread of the workgroup; call before
+// __syncthreads().
+__device__ inline void fill_exp_table(double* tab) {
+  for (int j = (int)threadIdx.x; j < kExpTable; j += (int)blockDim.x) tab[j] = exp_table_entry(j);
+}
 
 // Without the NaN pass-through (one compare and two selects fewer), for the exchange sums: a NaN
 // argument gives a finite weight there, but the NaN that caused it (a coordinate) also enters the
 // weighted payload sums, which take it on.
 __host__ __device__ inline double fast_exp_finite(double x, const double* tab) {
-  const double kInvL = 92.33248261689366;          // 64 / ln 2
-  const double kL1 = 0x1.62e42fee00000p-7;         // high 32 bits of ln2 / 64
-  const double kL2 = 0x1.a39ef35793c76p-39;        // ln2 / 64 - kL1
+  const double kInvL = 369.3299304675746;          // 256 / ln 2
+  const double kL1 = 0x1.62e42fee00000p-9;         // high 32 bits of ln2 / 256
+  const double kL2 = 0x1.a39ef35793c76p-41;        // ln2 / 256 - kL1
   const double kShift = 6755399441055744.0;        // 1.5 * 2^52
   const double xc = fmin(fmax(x, -800.0), 709.8);  // -inf -> -800 -> 0; NaN -> -800
   const double kds = fma(xc, kInvL, kShift);       // 1.5 * 2^52 + k
@@ -40,13 +45,12 @@ __host__ __device__ inline double fast_exp_finite(double x, const double* tab) {
   const double kd = kds - kShift;
   double r = fma(-kd, kL1, xc);
   r = fma(-kd, kL2, r);
-  const int j = k & 63;
-  const int m = (k - j) >> 6;                      // k - j is a multiple of 64
-  // e^r - 1 = r + r^2/2 + r^3/6 + r^4/24 + r^5/120
-  double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-  q = fma(q, r, 1.0 / 6.0);
+  const int j = k & (kExpTable - 1);
+  const int m = k >> 8;                            // floor(k / 256): k = 256 m + j
+  // e^r - 1 = r + r^2 (1/2 + r (1/6 + r/24))
+  double q = fma(r, 1.0 / 24.0, 1.0 / 6.0);
   q = fma(q, r, 0.5);
-  q = q * r * r + r;
+  q = fma(q, r * r, r);
   const double t = tab[j];
   return ldexp(fma(t, q, t), m);
 }

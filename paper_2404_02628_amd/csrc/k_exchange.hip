@@ -757,7 +757,7 @@ __global__ __launch_bounds__(64 * W) void k_recursion(const RepDev* __restrict__
   const int nblk = (N + 1 + kTile - 1) / kTile;   // rows 0..N
   const long long npp = R.npp;
 
-  if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
+  fill_exp_table(sh.tab);
   link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0], false);
   Prefetch<D> pf;
   pf.load(mp, 0, wave == 0);
@@ -938,7 +938,7 @@ __global__ __launch_bounds__(64 * kCoopWaves) void k_recursion_coop(const RepDev
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (N + 1 + kTile - 1) / kTile;
   const long long npp = R.npp;
-  if (threadIdx.x < kExpTable) sh.tab[threadIdx.x] = exp_table_entry(threadIdx.x);
+  fill_exp_table(sh.tab);
 
   if (is_chain) {
     link_prefix<D>(mp, 1.0 / R.c, lam, &sh.pm[0][0], true);   // before panel 0 is published

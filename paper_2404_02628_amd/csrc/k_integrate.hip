@@ -9,7 +9,6 @@
 // All of it is FP64 and elementwise over degrees of freedom (HBM-bound).
 #include "pimd_internal.h"
 #include "device_util.h"
-#include "fast_exp.h"
 #include "nhc.h"
 
 namespace pimd {
@@ -30,12 +29,12 @@ template <int M, int MODE>
 __device__ inline void integrate_one(const RepDev& R, int rep, long long gi, double fv, double fpv, double pv,
                                      double xv, double& es, double (&v)[M > 0 ? M : 1], double* __restrict__ x,
                                      double* __restrict__ p, double* __restrict__ f, double* __restrict__ veta,
-                                     long long G, double hdt, const SyW& sy, const double* tab, int* status) {
+                                     long long G, double hdt, const SyW& sy, int* status) {
   constexpr bool kPair = MODE != 0;
   constexpr bool kChain = M > 0 && MODE != 2;
   if (kPair) fv = R.amp > 0.0 ? fv + fpv : fv;
   if (MODE == 0) {
-    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
     pv += hdt * fv;
     const double xn = xv + R.dt_mp * pv;
     if (!isfinite(fv) || !isfinite(xn)) status_nonfinite(status, rep);
@@ -50,11 +49,11 @@ __device__ inline void integrate_one(const RepDev& R, int rep, long long gi, dou
       return;
     }
     pv += hdt * fv;
-    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy, tab);
+    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
     double xn = 0.0;
     if (MODE == 3) {
       // second thermostat half-step of this step and first of the next, chain in registers
-      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy, tab);
+      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
       pv += hdt * fv;
       xn = xv + R.dt_mp * pv;
       x[gi] = xn;
@@ -75,15 +74,14 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
                                                          const double* __restrict__ fpair,
                                                          double* __restrict__ etasum, double* __restrict__ veta,
                                                          long long G, SyW sy, int* status) {
-  __shared__ double tab[kExpTable];
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
   const long long li = (long long)wk.y + threadIdx.x;
   const bool ok = li < R.ndof;
   const long long gi = R.dof + (ok ? li : 0);
   const double hdt = 0.5 * R.dt;
-  // Every operand is loaded up front (before the table barrier), so a thread waits out one
-  // memory latency rather than one per dependence.  The pair forces are read even without a
+  // Every operand is loaded up front, so a thread waits out one memory latency rather than one
+  // per dependence.  The pair forces are read even without a
   // pair term (the buffer is part of the workspace either way) and selected away.
   constexpr bool kX = MODE == 0 || MODE == 3;
   constexpr bool kP = MODE != 2;
@@ -98,16 +96,12 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
 #pragma unroll
   for (int k = 0; k < (M > 0 ? M : 1); ++k) v[k] = kChain ? veta[k * G + gi] : 0.0;
   if constexpr (kChain) {
-    if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
-    __syncthreads();
     // every lane takes part in its wave's chain-position sum, so none leaves before it
-    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, tab,
-                                              status);
+    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, status);
     es = wave_sum(es);
     if ((threadIdx.x & 63) == 0 && !halted) etasum[(long long)blockIdx.x * kEtaSlots + (threadIdx.x >> 6)] += es;
   } else {
-    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, tab,
-                                              status);
+    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, status);
   }
 }
 

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_pair_f64(const RepDev* __restrict__ rep
   constexpr int IT = 4 / JS;
   __shared__ double red[4][D + 2][64];
   __shared__ double tab[kExpTable];   // table of the branch-free exponential (2 ulp)
-  if (threadIdx.x < kExpTable) tab[threadIdx.x] = exp_table_entry(threadIdx.x);
+  fill_exp_table(tab);
   __syncthreads();
   const int g = xcd_work_index((int)blockIdx.x, (int)gridDim.x);
   const int4 wk = work[g];

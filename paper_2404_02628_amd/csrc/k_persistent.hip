@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
   const int ca = own ? t / PN : 0, cj = own ? (t / N) % P : 0, cl = own ? t % N : 0;
   const long long gi = R.dof + t;
   const long long G = A.G;
-  if (t < kExpTable) sh.tab[t] = exp_table_entry(t);
+  fill_exp_table(sh.tab);
   if (t == 0) sh.halt = status_halted(A.status) ? 1 : 0;
   // es: the sum of this coordinate's chain positions (they only enter H', so one number per
   // coordinate is kept instead of one per chain element; it stays with the thread across launches)
@@ -287,14 +287,14 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
     const long long stp = A.step0 + it + 1;
     const bool smp = A.sample_every > 0 && (stp % A.sample_every == 0);
     if (own) {
-      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy, sh.tab);
+      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy);
       pv += hdt * fv;
       xv += R.dt_mp * pv;
     }
     fv = persist_evaluate<D>(sh, R, P, t, own, ca, cj, cl, xv, smp, en);
     if (own) {
       pv += hdt * fv;
-      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy, sh.tab);
+      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy);
     }
     if (smp) {
       double kv[2] = {0.0, 0.0};

@@ -7,7 +7,6 @@
 // paths apply the same arithmetic to every degree of freedom.
 #pragma once
 #include <hip/hip_runtime.h>
-#include "fast_exp.h"
 
 namespace pimd {
 
@@ -15,8 +14,9 @@ struct SyW { double w[5]; int n; };
 
 // exp(x) for the thermostat scale factors, whose arguments (h v / 4 and h v with h a fraction
 // of dt) are small: when every lane of the wavefront has |x| <= 1/32 the Taylor polynomial of
-// degree 8 (remainder below 2e-19 relative) replaces the table-driven exponential.
-__device__ inline double chain_exp(double x, const double* tab) {
+// degree 8 (remainder below 2e-19 relative) replaces the library exponential (which the
+// wavefront then only runs for chains far from equilibrium).
+__device__ inline double chain_exp(double x) {
   if (__all(fabs(x) <= 0.03125)) {
     double q = fma(x, 1.0 / 40320.0, 1.0 / 5040.0);
     q = fma(q, x, 1.0 / 720.0);
@@ -27,7 +27,7 @@ __device__ inline double chain_exp(double x, const double* tab) {
     q = fma(q, x, 1.0);
     return fma(q, x, 1.0);
   }
-  return fast_exp(x, tab);
+  return exp(x);
 }
 
 // The chain forces are G_1 = (p^2/m' - kT)/Q and G_k = (Q v_{k-1}^2 - kT)/Q = v_{k-1}^2 - kT/Q,
@@ -37,7 +37,7 @@ __device__ inline double chain_exp(double x, const double* tab) {
 // H' (through kT sum_k eta_k), so the propagator adds their increments h v_k into one number,
 // eta_sum, instead of keeping every eta_k.
 __device__ inline void nhc_propagate(double& p, double inv_mp, double& eta_sum, double* v, int M, double inv_q,
-                                     double kT, double tau, const SyW& sy, const double* tab) {
+                                     double kT, double tau, const SyW& sy) {
   const double kTq = kT * inv_q;
   for (int iw = 0; iw < sy.n; ++iw) {
     const double h = sy.w[iw] * tau;
@@ -47,11 +47,11 @@ __device__ inline void nhc_propagate(double& p, double inv_mp, double& eta_sum, 
       v[M - 1] += 0.5 * h * Gm;
     }
     for (int k = M - 2; k >= 0; --k) {
-      sc[k] = chain_exp(-0.25 * h * v[k + 1], tab);
+      sc[k] = chain_exp(-0.25 * h * v[k + 1]);
       double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
       v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];
     }
-    p *= chain_exp(-h * v[0], tab);
+    p *= chain_exp(-h * v[0]);
     double vs = 0.0;
     for (int k = 0; k < M; ++k) vs += v[k];
     eta_sum = fma(h, vs, eta_sum);

@@ -25,9 +25,8 @@
 //            per chain step (the multiply keeps the chain's value in range), so the
 //            instruction's own cost is the kind's figure minus `f64:mul`:
 //            fma, mul, add, max, ldexp, rndne, cvt (double -> int -> double counts two)
-//   exp64:*  the FP64 exponential's throughput per call: `table` the library's table-driven
-//            exp (fast_exp.h); `shift` the same with the rounding to an integer done by adding
-//            and subtracting 1.5 * 2^52 (no rndne, no conversion; the integer is the low word)
+//   exp64    the library's FP64 exponential (fast_exp.h): throughput per call, plus one add and
+//            the multiply
 // The results decide the pair kernel's design: whether a Gram-matrix formulation on the matrix
 // cores (|r_i - r_j|^2 = |r_i|^2 + |r_j|^2 - 2 r_i.r_j) can beat the plain vector form; and the
 // FP64 exponential's form in the exchange sums and the FP64 pair kernel.
@@ -141,31 +140,12 @@ __global__ __launch_bounds__(kThreads) void k_pair(float* out, int iters) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
-enum F64Kind { kF64Fma, kF64Mul, kF64Add, kF64Max, kF64Ldexp, kF64Rndne, kF64Cvt, kExpTable64, kExpShift64 };
-
-// the table exponential with the magic-number rounding: kd_s = x 64/ln2 + 1.5 * 2^52 rounds to an
-// integer k held in the low word of kd_s (|k| < 2^31 for x in [-800, 709.8])
-__device__ inline double exp_shift(double x, const double* tab) {
-  const double kInvL = 92.33248261689366, kShift = 6755399441055744.0;   // 64/ln2, 1.5 * 2^52
-  const double kL1 = 0x1.62e42fee00000p-7, kL2 = 0x1.a39ef35793c76p-39;
-  const double xc = fmin(fmax(x, -800.0), 709.8);
-  const double kds = fma(xc, kInvL, kShift);
-  const int k = (int)(unsigned)__double_as_longlong(kds);
-  const double kd = kds - kShift;
-  double r = fma(-kd, kL1, xc);
-  r = fma(-kd, kL2, r);
-  double q = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-  q = fma(q, r, 1.0 / 6.0);
-  q = fma(q, r, 0.5);
-  q = q * r * r + r;
-  const double t = tab[k & 63];
-  return ldexp(fma(t, q, t), k >> 6);
-}
+enum F64Kind { kF64Fma, kF64Mul, kF64Add, kF64Max, kF64Ldexp, kF64Rndne, kF64Cvt, kExp64 };
 
 template <int KIND>
 __global__ __launch_bounds__(kThreads) void k_f64(float* out, int iters) {
   __shared__ double tab[pimd::kExpTable];
-  if (threadIdx.x < pimd::kExpTable) tab[threadIdx.x] = pimd::exp_table_entry(threadIdx.x);
+  pimd::fill_exp_table(tab);
   __syncthreads();
   double v[8];
   for (int q = 0; q < 8; ++q) v[q] = 0.5 + 0.01 * q + threadIdx.x * 1e-5;
@@ -181,8 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_f64(float* out, int iters) {
       if (KIND == kF64Ldexp) w = ldexp(w, e);
       if (KIND == kF64Rndne) w = rint(w);
       if (KIND == kF64Cvt) w = (double)(int)w + c;
-      if (KIND == kExpTable64) w = pimd::fast_exp_finite(-w, tab) + c;
-      if (KIND == kExpShift64) w = exp_shift(-w, tab) + c;
+      if (KIND == kExp64) w = pimd::fast_exp_finite(-w, tab) + c;
       v[q] = w * 0.9999;   // the multiply every kind carries (f64:mul alone is just this)
     }
   }
@@ -246,7 +225,7 @@ static double stream_gbs(L launch, double bytes) {
 // One wavefront: a dependent chain of two-term log-sum-exps (see lse2 above).
 __global__ __launch_bounds__(64) void k_lse2_chain(double* out, int iters) {
   __shared__ double tab[pimd::kExpTable];
-  tab[threadIdx.x] = pimd::exp_table_entry(threadIdx.x);   // 64 threads fill the 64 entries
+  pimd::fill_exp_table(tab);
   __syncthreads();
   double x = 0.1 * threadIdx.x;
   const double a = 1.0 + 1e-3 * threadIdx.x, c = 0.25;
@@ -307,8 +286,7 @@ int main() {
     f64("f64:ldexp", k_f64<kF64Ldexp>);
     f64("f64:rndne", k_f64<kF64Rndne>);
     f64("f64:cvt", k_f64<kF64Cvt>);
-    f64("exp64:table", k_f64<kExpTable64>);
-    f64("exp64:shift", k_f64<kExpShift64>);
+    f64("exp64", k_f64<kExp64>);
   }
   CK(hipFree(out));
 

@@ -6,8 +6,8 @@
 #include "../../paper_2404_02628_amd/csrc/fast_exp.h"
 
 int main() {
-  double tab[64];
-  for (int j = 0; j < 64; ++j) tab[j] = pimd::exp_table_entry(j);
+  double tab[pimd::kExpTable];
+  for (int j = 0; j < pimd::kExpTable; ++j) tab[j] = pimd::exp_table_entry(j);
   double worst = 0.0, worst_x = 0.0;
   long n = 0;
   uint64_t s = 88172645463325252ull;
