@@ -191,7 +191,7 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
     R.rw0 = R.spw0; R.rw1 = R.spw1;
     R.iw0 = nint;
     for (long long d0 = 0; d0 < R.ndof; d0 += kIntBlock, ++nint)
-      if (lists) pl.intwork.push_back(make_int4(r, (int)d0, 0, 0));
+      if (lists) pl.intwork.push_back(int_work_item(r, R.dof + d0, std::min<long long>(kIntBlock, R.ndof - d0)));
     R.iw1 = nint;
     if (lists) pl.reps[r] = R;
     if (r == 0) pl.rep0 = R;
@@ -577,7 +577,8 @@ __global__ void k_noalloc_prepare(RepDev rep0, DevPtrs w, long long nspring, lon
   for (long long k = t0; k < nspring; k += stride) w.springwork[k] = make_int4(0, (int)(k * kSpringBlock), 0, 0);
   for (long long k = t0; k < npair; k += stride)
     w.pairwork[k] = make_int4(0, (int)(k / per_slice), (int)(k % per_slice) * ipw, 0);
-  for (long long k = t0; k < nint; k += stride) w.intwork[k] = make_int4(0, (int)(k * kIntBlock), 0, 0);
+  for (long long k = t0; k < nint; k += stride)
+    w.intwork[k] = int_work_item(0, rep0.dof + k * kIntBlock, min((long long)kIntBlock, rep0.ndof - k * kIntBlock));
   for (long long k = t0; k < nflags; k += stride) w.flags[k] = 0;
 }
 

@@ -50,9 +50,9 @@ __global__ __launch_bounds__(kIntBlock) void k_init_state(const RepDev* __restri
                                                           double* __restrict__ veta, long long G, int M) {
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
-  const long long li = (long long)wk.y + threadIdx.x;
-  if (li >= R.ndof) return;
-  const long long gi = R.dof + li;
+  if ((int)threadIdx.x >= wk.y) return;
+  const long long gi = int_work_first(wk) + threadIdx.x;
+  const long long li = gi - R.dof;   // index within the replica (the generator's counter)
   const double sigma = params[2LL * wk.x];
   const unsigned long long seed = (unsigned long long)__double_as_longlong(params[2LL * wk.x + 1]);
   x[gi] = sigma * gaussian(seed, 0u, (unsigned long long)li);

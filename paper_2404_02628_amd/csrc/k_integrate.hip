@@ -24,12 +24,15 @@ namespace pimd {
 // are kept as sums only (they enter nothing but H'): each wave adds its increment to its own
 // slot of etasum, in a fixed order, so the sums are reproducible.
 // One degree of freedom of k_integrate, from its operands in registers: writes x, p, f and the
-// chain velocities; the chain-position increments go to es.
+// chain velocities (and raises the status word on a non-finite value) only when `store` is set;
+// the chain-position increments go to es.  The arithmetic runs whether or not the lane stores, so
+// that its operands are loaded unconditionally at the top of the kernel and the status word is
+// only waited for at the first store.
 template <int M, int MODE>
 __device__ inline void integrate_one(const RepDev& R, int rep, long long gi, double fv, double fpv, double pv,
                                      double xv, double& es, double (&v)[M > 0 ? M : 1], double* __restrict__ x,
                                      double* __restrict__ p, double* __restrict__ f, double* __restrict__ veta,
-                                     long long G, double hdt, const SyW& sy, int* status) {
+                                     long long G, double hdt, const SyW& sy, bool store, int* status) {
   constexpr bool kPair = MODE != 0;
   constexpr bool kChain = M > 0 && MODE != 2;
   if (kPair) fv = R.amp > 0.0 ? fv + fpv : fv;
@@ -37,17 +40,18 @@ __device__ inline void integrate_one(const RepDev& R, int rep, long long gi, dou
     if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
     pv += hdt * fv;
     const double xn = xv + R.dt_mp * pv;
+    if (!store) return;
     if (!isfinite(fv) || !isfinite(xn)) status_nonfinite(status, rep);
     x[gi] = xn;
     p[gi] = pv;
   } else {
-    // the total force is kept for readers of the last evaluation; in the fused pass the next
-    // evaluation overwrites it unread
-    if (MODE != 3) f[gi] = fv;
     if (MODE == 2) {
+      if (!store) return;
+      f[gi] = fv;
       if (!isfinite(fv)) status_nonfinite(status, rep);
       return;
     }
+    const double ftot = fv;
     pv += hdt * fv;
     if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
     double xn = 0.0;
@@ -56,8 +60,12 @@ __device__ inline void integrate_one(const RepDev& R, int rep, long long gi, dou
       if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
       pv += hdt * fv;
       xn = xv + R.dt_mp * pv;
-      x[gi] = xn;
     }
+    if (!store) return;
+    // the total force is kept for readers of the last evaluation; in the fused pass the next
+    // evaluation overwrites it unread
+    if (MODE != 3) f[gi] = ftot;
+    if (MODE == 3) x[gi] = xn;
     if (!isfinite(fv) || !isfinite(pv) || !isfinite(xn)) status_nonfinite(status, rep);
     p[gi] = pv;
   }
@@ -75,14 +83,13 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
                                                          double* __restrict__ etasum, double* __restrict__ veta,
                                                          long long G, SyW sy, int* status) {
   const int4 wk = work[blockIdx.x];
-  const RepDev& R = reps[wk.x];
-  const long long li = (long long)wk.y + threadIdx.x;
-  const bool ok = li < R.ndof;
-  const long long gi = R.dof + (ok ? li : 0);
+  const bool ok = (int)threadIdx.x < wk.y;
+  const long long gi = int_work_first(wk) + (ok ? (int)threadIdx.x : 0);
+  const RepDev& R = reps[wk.x];   // read while the loads below are in flight
   const double hdt = 0.5 * R.dt;
   // Every operand is loaded up front, so a thread waits out one memory latency rather than one
-  // per dependence.  The pair forces are read even without a
-  // pair term (the buffer is part of the workspace either way) and selected away.
+  // per dependence.  The pair forces are read even without a pair term (the buffer is part of
+  // the workspace either way) and selected away.
   constexpr bool kX = MODE == 0 || MODE == 3;
   constexpr bool kP = MODE != 2;
   constexpr bool kPair = MODE != 0;
@@ -95,13 +102,12 @@ __global__ __launch_bounds__(kIntBlock) void k_integrate(const RepDev* __restric
   double es = 0.0, v[M > 0 ? M : 1];
 #pragma unroll
   for (int k = 0; k < (M > 0 ? M : 1); ++k) v[k] = kChain ? veta[k * G + gi] : 0.0;
+  const bool store = ok && !halted;
+  integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, store, status);
   if constexpr (kChain) {
-    // every lane takes part in its wave's chain-position sum, so none leaves before it
-    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, status);
-    es = wave_sum(es);
+    // every lane takes part in its wave's chain-position sum
+    es = wave_sum(store ? es : 0.0);
     if ((threadIdx.x & 63) == 0 && !halted) etasum[(long long)blockIdx.x * kEtaSlots + (threadIdx.x >> 6)] += es;
-  } else {
-    if (ok && !halted) integrate_one<M, MODE>(R, wk.x, gi, fv, fpv, pv, xv, es, v, x, p, f, veta, G, hdt, sy, status);
   }
 }
 

@@ -16,6 +16,16 @@ constexpr int kSpringBlock = 256;  // particles per spring-kernel workgroup
 constexpr int kIntBlock = 256;     // degrees of freedom per integrator workgroup
 constexpr int kEtaSlots = kIntBlock / 64;   // chain-position sums per integrator work item (one per wave)
 
+// Integrator work item: replica r, the `count` degrees of freedom from global index g0 on.  The
+// global index is stored directly so that the integrator issues its loads after reading the work
+// item alone, not after the replica's record as well.
+__host__ __device__ inline int4 int_work_item(int r, long long g0, long long count) {
+  return make_int4(r, (int)count, (int)(unsigned)(g0 & 0xffffffffLL), (int)(g0 >> 32));
+}
+__host__ __device__ inline long long int_work_first(const int4& wk) {
+  return ((long long)wk.w << 32) | (long long)(unsigned)wk.z;
+}
+
 // Energy record slots (per replica, and per trace sample).
 enum RecSlot {
   kVExch = 0, kUTrap, kUPair, kSpring, kVirial, kEPrim, kEVir, kKinetic, kNhcE, kHCons, kStep,
@@ -87,7 +97,7 @@ struct DevPtrs {
   int4* springwork;            // {rep, l0, 0, 0}
   int4* pairwork;              // {rep, slice, i0, 0}
   int4* reducework;            // {rep, l0, 0, 0}
-  int4* intwork;               // {rep, first dof, 0, 0}
+  int4* intwork;               // {rep, dofs, first global dof (low word, high word)}: see int_work_item
   int* reporder;               // [R] replica of the k-th recursion workgroup pair (launch order)
   double* dbg;                 // debug scratch (N+2 doubles of the largest replica, x2)
 };
@@ -109,9 +119,11 @@ constexpr int kNonfiniteBase = 0x7fffffff;
 
 // A raised status word halts the dynamics: the integrator, the estimators and the density stop
 // writing, so the state and the accumulators stay as they were when the failure was detected.
+// Both words are read together (one memory round trip, not two).
 __device__ inline bool status_halted(const int* err) {
-  return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-         __hip_atomic_load(err + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  const int a = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int b = __hip_atomic_load(err + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (a | b) != 0;
 }
 
 // Records that replica r produced a non-finite value (the lowest such replica wins).

@@ -16,6 +16,11 @@
 //   copy, copy4, triad   FP64 streams over 512 MiB arrays (y = x; z = x + s y) in two launch
 //            shapes: what a plain kernel gets out of HBM, for comparison with the memory-bound
 //            kernels (springs, integrator)
+//   int14, int8   the fused integrator's HBM pattern over 13.1M degrees of freedom (128 replicas
+//            of 1600 particles, 32 beads, d = 2): per degree of freedom 8 doubles read and 6
+//            written, either as 14 separate arrays (the thermostat's 4 chain velocities in
+//            4 arrays, as the library stores them) or with the 4 chain velocities of a degree of
+//            freedom next to each other (8 streams: one 32-byte read and write instead of 4)
 //   lse2     latency, not throughput: one wavefront runs X <- -log(a + exp(c - X)) with the
 //            library's FP64 exponential and logarithm, every iteration depending on the last.
 //            This is the least a sequential exchange recursion (Eqs. 6, 11) must spend per row
@@ -198,6 +203,38 @@ __global__ __launch_bounds__(256) void k_triad(const double2* __restrict__ x, co
   }
 }
 
+// the integrator's streams: f, fp, p, x, v0..v3 read; x, p, v0..v3 written (separate arrays)
+__global__ __launch_bounds__(256) void k_int14(const double* __restrict__ f, const double* __restrict__ fp,
+                                               double* __restrict__ p, double* __restrict__ x,
+                                               double* __restrict__ v, long long n) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const double a = f[i] + fp[i], pv = p[i], xv = x[i];
+  double w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = v[k * n + i];
+  const double pn = fma(0.01, a, pv) * (1.0 - 1e-3 * w[0]);
+  x[i] = fma(0.01, pn, xv);
+  p[i] = pn;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k * n + i] = fma(w[k], 0.999, 1e-3 * a);
+}
+
+// the same with the four chain velocities of a degree of freedom in one 32-byte record
+__global__ __launch_bounds__(256) void k_int8(const double* __restrict__ f, const double* __restrict__ fp,
+                                              double* __restrict__ p, double* __restrict__ x,
+                                              double4* __restrict__ v, long long n) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const double a = f[i] + fp[i], pv = p[i], xv = x[i];
+  const double4 w = v[i];
+  const double pn = fma(0.01, a, pv) * (1.0 - 1e-3 * w.x);
+  x[i] = fma(0.01, pn, xv);
+  p[i] = pn;
+  v[i] = make_double4(fma(w.x, 0.999, 1e-3 * a), fma(w.y, 0.999, 1e-3 * a), fma(w.z, 0.999, 1e-3 * a),
+                      fma(w.w, 0.999, 1e-3 * a));
+}
+
 // best of five launches, in GB/s for `bytes` moved per launch
 template <typename L>
 static double stream_gbs(L launch, double bytes) {
@@ -339,5 +376,34 @@ int main() {
   CK(hipFree(x));
   CK(hipFree(y));
   CK(hipFree(z));
+
+  {
+    const long long nd = 128LL * 1600 * 32 * 2;   // degrees of freedom
+    double *f = nullptr, *fp = nullptr, *pp = nullptr, *xx = nullptr, *vv = nullptr;
+    CK(hipMalloc(&f, nd * sizeof(double)));
+    CK(hipMalloc(&fp, nd * sizeof(double)));
+    CK(hipMalloc(&pp, nd * sizeof(double)));
+    CK(hipMalloc(&xx, nd * sizeof(double)));
+    CK(hipMalloc(&vv, 4 * nd * sizeof(double)));
+    CK(hipMemset(f, 0, nd * sizeof(double)));
+    CK(hipMemset(fp, 0, nd * sizeof(double)));
+    CK(hipMemset(pp, 0, nd * sizeof(double)));
+    CK(hipMemset(xx, 0, nd * sizeof(double)));
+    CK(hipMemset(vv, 0, 4 * nd * sizeof(double)));
+    const unsigned gi = (unsigned)((nd + 255) / 256);
+    const double bytes = 14.0 * 8.0 * nd;
+    const double g14 = stream_gbs([&] { hipLaunchKernelGGL(k_int14, dim3(gi), dim3(256), 0, 0, f, fp, pp, xx, vv, nd); },
+                                  bytes);
+    std::printf("int14   %8.1f GB/s (%.1f us; 14 arrays of 8-byte elements)\n", g14, bytes / g14 * 1e-3);
+    const double g8 = stream_gbs([&] { hipLaunchKernelGGL(k_int8, dim3(gi), dim3(256), 0, 0, f, fp, pp, xx,
+                                                          (double4*)vv, nd); },
+                                 bytes);
+    std::printf("int8    %8.1f GB/s (%.1f us; chain velocities as 32-byte records)\n", g8, bytes / g8 * 1e-3);
+    CK(hipFree(f));
+    CK(hipFree(fp));
+    CK(hipFree(pp));
+    CK(hipFree(xx));
+    CK(hipFree(vv));
+  }
   return 0;
 }
