@@ -14,12 +14,11 @@ struct SyW { double w[5]; int n; };
 
 // exp(x) for the thermostat scale factors, whose arguments (h v / 4 and h v with h a fraction
 // of dt) are small: when every lane of the wavefront has |x| <= 1/32 the Taylor polynomial of
-// degree 8 (remainder below 2e-19 relative) replaces the library exponential (which the
+// degree 7 (remainder below 3e-17 relative) replaces the library exponential (which the
 // wavefront then only runs for chains far from equilibrium).
 __device__ inline double chain_exp(double x) {
   if (__all(fabs(x) <= 0.03125)) {
-    double q = fma(x, 1.0 / 40320.0, 1.0 / 5040.0);
-    q = fma(q, x, 1.0 / 720.0);
+    double q = fma(x, 1.0 / 5040.0, 1.0 / 720.0);
     q = fma(q, x, 1.0 / 120.0);
     q = fma(q, x, 1.0 / 24.0);
     q = fma(q, x, 1.0 / 6.0);
