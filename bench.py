@@ -120,7 +120,7 @@ def algorithmic_work(kind, systems, P, D, precision="mixed"):
     return "hbm", dofs, 8, "GB/s", PEAK_HBM_GBS
 
 
-KERNEL_OF_KIND = {("pair", "mixed"): "k_pair_sym_f32", ("pair", "fp64"): "k_pair_f64",
+KERNEL_OF_KIND = {("pair", "mixed"): "k_pair_sym_f32", ("pair", "fp64"): "k_pair_sym_f64",
                   ("recursion", "mixed"): "k_recursion", ("recursion", "fp64"): "k_recursion"}
 
 

@@ -43,7 +43,8 @@ const char* kKindNames[K_COUNT] = {"springs", "pair", "recursion", "exchange_for
                                    "persistent_steps"};
 
 // LDS one workgroup may hold on gfx950 (160 KiB per compute unit): the symmetric pair kernel keeps a
-// whole slice there, which bounds the N it serves (6,400 particles in 2-D, 3,840 in 3-D, 12,864 in 1-D).
+// whole slice there, which bounds the N it serves (mixed: 6,400 particles in 2-D, 3,840 in 3-D,
+// 12,864 in 1-D; FP64: 4,416 in 2-D, 2,944 in 3-D, 8,896 in 1-D).
 constexpr int kMaxLdsBytes = 160 * 1024;
 
 // Steps per launch of the persistent kernel (a call with more steps is split).
@@ -129,8 +130,8 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
   d.R = c->n_replicas; d.P = c->p; d.D = c->dim; d.M = c->nhc_len; d.precision = c->precision;
   d.sy_order = c->sy_order; d.bins = c->density_bins; d.cap = c->trace_capacity; d.rmax = c->density_rmax;
   const int dp = shadow_dp(d.D);
-  // Pair kernel: with many interacting slices (mixed precision), one workgroup per slice that
-  // evaluates each unordered pair once; otherwise the ordered kernel, split so that there are
+  // Pair kernel: with many interacting slices, one workgroup per slice that evaluates each
+  // unordered pair once (either precision); otherwise the ordered kernel, split so that there are
   // enough waves to cover the machine (256 CUs x 4 SIMDs x ~2).
   long long tiles64 = 0, pair_slices = 0;
   int pair_maxn = 0;
@@ -140,7 +141,7 @@ void make_plan(const pimd_config* c, Plan& pl, bool lists = true) {
       pair_slices += d.P;
       pair_maxn = std::max(pair_maxn, c->replicas[r].n);
     }
-  const bool sym = d.precision == PIMD_MIXED && pair_slices >= 256 && pair_sym_lds_bytes(d.D, pair_maxn) <= kMaxLdsBytes &&
+  const bool sym = pair_slices >= 256 && pair_sym_lds_bytes(d.D, pair_maxn, d.precision) <= kMaxLdsBytes &&
                    (c->flags & PIMD_FLAG_PAIR_ORDERED) == 0;
   const int split_code = (c->flags & PIMD_FLAG_PAIR_SPLIT_MASK) / PIMD_FLAG_PAIR_SPLIT_1;   // 0, 1, 2, 3
   const int forced_split = split_code == 0 ? 0 : (1 << (split_code - 1));                   // 0, 1, 2, 4

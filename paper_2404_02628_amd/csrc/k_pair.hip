@@ -218,53 +218,71 @@ static void launch_pair_js(const Dims& d, const DevPtrs& w, int js, hipStream_t 
 // the LDS force updates need no atomics and their order is fixed (results are reproducible).
 // The diagonal tiles (I, I) run first with the pairs j <= i masked out.  Padding particles sit
 // at distinct far-away positions, so their terms underflow to exactly zero.
+//
+// Two precisions share this schedule.  Mixed (T = float): the FP32 shadow, pre-scaled so that a
+// term is exp2(-|dr|^2) (one v_exp_f32), tile sums in FP32.  FP64 (T = double): the positions
+// scaled by 1/s, a term is exp(-|dr|^2) by the table exponential (its table in LDS), everything
+// in FP64.
 constexpr int kSymWaves = 4;
 constexpr int kRedStride = 9;   // LDS row stride of the per-wave transpose (conflict-free reads)
 
-template <int D>
+template <class T> struct SymPrec;
+template <> struct SymPrec<float> {
+  template <int D> static constexpr int dp() { return D == 3 ? 4 : D; }   // shadow row (float4 in 3-D)
+  static constexpr int kTab = 0;
+  static __device__ inline float term(float r2, const double*) { return __builtin_amdgcn_exp2f(-r2); }
+};
+template <> struct SymPrec<double> {
+  template <int D> static constexpr int dp() { return D; }
+  static constexpr int kTab = kExpTable;
+  static __device__ inline double term(double r2, const double* tab) { return fast_exp_finite(-r2, tab); }
+};
+
+template <class T, int D>
 __host__ __device__ inline int sym_lds_bytes(int npad) {
-  constexpr int DP = D == 3 ? 4 : D;
-  return npad * (DP * 4 + D * 8) + kSymWaves * 64 * kRedStride * 4 + 2 * kSymWaves * 8 * 2;
+  constexpr int DP = SymPrec<T>::template dp<D>();
+  return npad * (DP * (int)sizeof(T) + D * 8) + kSymWaves * 64 * kRedStride * (int)sizeof(T) + 2 * kSymWaves * 8 * 2 +
+         SymPrec<T>::kTab * 8;
 }
 
-template <int D, bool EST, bool DIAG>
-__device__ inline void sym_tile_pair(const float* __restrict__ pos, double* __restrict__ Fs, float* __restrict__ red,
-                                     int npad, int I, int J, double& Ud, double& Wd) {
-  constexpr int DP = D == 3 ? 4 : D;
+template <class T, int D, bool EST, bool DIAG>
+__device__ inline void sym_tile_pair(const T* __restrict__ pos, double* __restrict__ Fs, T* __restrict__ red,
+                                     const double* __restrict__ tab, int npad, int I, int J, double& Ud, double& Wd) {
+  constexpr int DP = SymPrec<T>::template dp<D>();
   const int lane = threadIdx.x & 63;
   const int c0 = lane & 7, k0 = lane >> 3;
-  float xi[8][D], xj[8][D], Fi[8][D], Fj[8][D];
+  T xi[8][D], xj[8][D], Fi[8][D], Fj[8][D];
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       xi[a][c] = pos[(I * 64 + c0 + 8 * a) * DP + c];
       xj[a][c] = pos[(J * 64 + k0 + 8 * a) * DP + c];
-      Fi[a][c] = 0.f;
-      Fj[a][c] = 0.f;
+      Fi[a][c] = T(0);
+      Fj[a][c] = T(0);
     }
   }
-  float U = 0.f, W = 0.f;
+  T U = T(0), W = T(0);
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      float d[D], r2 = 0.f;
+      T d[D], r2 = T(0);
 #pragma unroll
       for (int c = 0; c < D; ++c) {
         d[c] = xi[a][c] - xj[b][c];
-        r2 = __builtin_fmaf(d[c], d[c], r2);
+        r2 = fma(d[c], d[c], r2);
       }
-      float u = __builtin_amdgcn_exp2f(-r2);
-      if (DIAG) u = (k0 + 8 * b > c0 + 8 * a) ? u : 0.f;
+      T u = SymPrec<T>::term(r2, tab);
+      if (DIAG) u = (k0 + 8 * b > c0 + 8 * a) ? u : T(0);
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        Fi[a][c] = __builtin_fmaf(u, d[c], Fi[a][c]);
-        Fj[b][c] = __builtin_fmaf(-u, d[c], Fj[b][c]);
+        Fi[a][c] = fma(u, d[c], Fi[a][c]);
+        Fj[b][c] = fma(-u, d[c], Fj[b][c]);
       }
       if (EST) {
         U += u;
-        W = __builtin_fmaf(u, r2, W);
+        W = fma(u, r2, W);
       }
     }
   }
@@ -274,18 +292,104 @@ __device__ inline void sym_tile_pair(const float* __restrict__ pos, double* __re
   for (int c = 0; c < D; ++c) {
 #pragma unroll
     for (int a = 0; a < 8; ++a) red[lane * kRedStride + a] = Fi[a][c];
-    float si = 0.f;
+    T si = T(0);
 #pragma unroll
     for (int k = 0; k < 8; ++k) si += red[(c0 + 8 * k) * kRedStride + k0];
 #pragma unroll
     for (int b = 0; b < 8; ++b) red[lane * kRedStride + b] = Fj[b][c];
     // lane (c0, k0) sums particle k0 + 8 c0 of tile J over the eight lanes that share k0 (rows
     // q + 8 k0, column c0: distinct banks across each half wave)
-    float sj = 0.f;
+    T sj = T(0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) sj += red[(q + 8 * k0) * kRedStride + c0];
     Fs[c * npad + I * 64 + lane] += (double)si;
     Fs[c * npad + J * 64 + k0 + 8 * c0] += (double)sj;
+  }
+}
+
+// Slice positions into LDS: the mixed shadow as stored, or the FP64 positions scaled by 1/s.
+template <class T, int D>
+__device__ inline void sym_load_slice(T* __restrict__ pos, const RepDev& R, const float* __restrict__ xs,
+                                      const double* __restrict__ x, int slice, int P) {
+  constexpr int DP = SymPrec<T>::template dp<D>();
+  const int N = R.n, npad = R.npad;
+  if constexpr (sizeof(T) == 4) {
+    const float* xsl = xs + R.shadow + (long long)slice * npad * DP;
+    for (int l = threadIdx.x; l < npad; l += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < DP; ++c) pos[l * DP + c] = l < N ? xsl[(long long)l * DP + c] : 1.0e4f * (float)(l + 1);
+    }
+  } else {
+    const double inv_s = 1.0 / R.width;
+    const double* xr = x + R.dof;
+    for (int l = threadIdx.x; l < npad; l += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        pos[l * DP + c] = l < N ? xr[((long long)c * P + slice) * N + l] * inv_s : 1.0e4 * (double)(l + 1);
+    }
+  }
+}
+
+template <class T, int D, bool EST>
+__device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4* __restrict__ work,
+                                     const float* __restrict__ xs, const double* __restrict__ x,
+                                     double* __restrict__ fpair, double* __restrict__ pairpart, int P,
+                                     unsigned char* lds) {
+  constexpr int DP = SymPrec<T>::template dp<D>();
+  const int4 wk = work[blockIdx.x];
+  const RepDev& R = reps[wk.x];
+  const int N = R.n, slice = wk.y, npad = R.npad;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* Fs = reinterpret_cast<double*>(lds);                    // [D][npad]
+  double* tab = Fs + (long long)D * npad;                          // [kTab] (FP64 only)
+  T* pos = reinterpret_cast<T*>(tab + SymPrec<T>::kTab);           // [npad][DP]
+  T* red = pos + (long long)npad * DP + wave * 64 * kRedStride;
+  double* part = reinterpret_cast<double*>(pos + (long long)npad * DP + kSymWaves * 64 * kRedStride);
+  if constexpr (SymPrec<T>::kTab > 0) fill_exp_table(tab);
+  sym_load_slice<T, D>(pos, R, xs, x, slice, P);
+  for (int l = threadIdx.x; l < npad; l += blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) Fs[c * npad + l] = 0.0;
+  }
+  __syncthreads();
+  const int T_ = npad / 64;
+  double Ud = 0.0, Wd = 0.0;
+  for (int t = wave; t < T_; t += kSymWaves) sym_tile_pair<T, D, EST, true>(pos, Fs, red, tab, npad, t, t, Ud, Wd);
+  __syncthreads();
+  if (T_ > 1) {
+    const int Tp = T_ + (T_ & 1), m = Tp - 1;
+    for (int r = 0; r < m; ++r) {
+      for (int k = wave; k < Tp / 2; k += kSymWaves) {
+        const int p = k == 0 ? r : (r + k) % m;
+        const int q = k == 0 ? m : (r - k + m) % m;
+        if (p < T_ && q < T_) sym_tile_pair<T, D, EST, false>(pos, Fs, red, tab, npad, min(p, q), max(p, q), Ud, Wd);
+      }
+      __syncthreads();
+    }
+  }
+  // mixed: F = (2A/(P s^2 k)) sum u (r'_i - r'_j) with r' = k r, k = sqrt(log2 e)/s;
+  // FP64:  F = (2A/(P s)) sum u (r'_i - r'_j) with r' = r/s
+  const double kk = sizeof(T) == 4 ? sqrt(1.4426950408889634) / R.width : 1.0 / R.width;
+  const double scale = 2.0 * R.amp / ((double)P * R.width * R.width * kk);
+  double* fr = fpair + R.dof;
+  for (int l = threadIdx.x; l < N; l += blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) fr[((long long)c * P + slice) * N + l] = scale * Fs[c * npad + l];
+  }
+  if (EST) {
+    // unordered pairs: U_slice = A sum u, virial part A sum u (1 - r^2/s^2)
+    // (mixed: r'^2 = r^2 log2(e)/s^2, so r^2/s^2 = r'^2 / log2(e))
+    Ud = wave_sum(Ud);
+    Wd = wave_sum(Wd);
+    if (lane == 0) { part[2 * wave] = Ud; part[2 * wave + 1] = Wd; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double u = 0.0, w = 0.0;
+      for (int q = 0; q < kSymWaves; ++q) { u += part[2 * q]; w += part[2 * q + 1]; }
+      const double wscale = sizeof(T) == 4 ? 1.0 / 1.4426950408889634 : 1.0;
+      pairpart[2LL * blockIdx.x + 0] = R.amp * u;
+      pairpart[2LL * blockIdx.x + 1] = R.amp * (u - w * wscale);
+    }
   }
 }
 
@@ -295,73 +399,37 @@ __global__ __launch_bounds__(kSymWaves * 64) void k_pair_sym_f32(const RepDev* _
                                                                  const float* __restrict__ xs,
                                                                  double* __restrict__ fpair,
                                                                  double* __restrict__ pairpart, int P) {
-  constexpr int DP = D == 3 ? 4 : D;
   extern __shared__ __align__(16) unsigned char sym_lds[];
-  const int4 wk = work[blockIdx.x];
-  const RepDev& R = reps[wk.x];
-  const int N = R.n, slice = wk.y, npad = R.npad;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* Fs = reinterpret_cast<double*>(sym_lds);                 // [D][npad]
-  float* pos = reinterpret_cast<float*>(Fs + (long long)D * npad);  // [npad][DP]
-  float* red = pos + (long long)npad * DP + wave * 64 * kRedStride;
-  double* part = reinterpret_cast<double*>(pos + (long long)npad * DP + kSymWaves * 64 * kRedStride);
-  const float* xsl = xs + R.shadow + (long long)slice * npad * DP;
-  for (int l = threadIdx.x; l < npad; l += blockDim.x) {
-#pragma unroll
-    for (int c = 0; c < DP; ++c) pos[l * DP + c] = l < N ? xsl[(long long)l * DP + c] : 1.0e4f * (float)(l + 1);
-#pragma unroll
-    for (int c = 0; c < D; ++c) Fs[c * npad + l] = 0.0;
-  }
-  __syncthreads();
-  const int T = npad / 64;
-  double Ud = 0.0, Wd = 0.0;
-  for (int t = wave; t < T; t += kSymWaves) sym_tile_pair<D, EST, true>(pos, Fs, red, npad, t, t, Ud, Wd);
-  __syncthreads();
-  if (T > 1) {
-    const int Tp = T + (T & 1), m = Tp - 1;
-    for (int r = 0; r < m; ++r) {
-      for (int k = wave; k < Tp / 2; k += kSymWaves) {
-        const int p = k == 0 ? r : (r + k) % m;
-        const int q = k == 0 ? m : (r - k + m) % m;
-        if (p < T && q < T) sym_tile_pair<D, EST, false>(pos, Fs, red, npad, min(p, q), max(p, q), Ud, Wd);
-      }
-      __syncthreads();
-    }
-  }
-  // F = (2A/(P s^2 k)) * sum u (r'_i - r'_j) with r' = k r, k = sqrt(log2 e)/s
-  const double kk = sqrt(1.4426950408889634) / R.width;
-  const double scale = 2.0 * R.amp / ((double)P * R.width * R.width * kk);
-  double* fr = fpair + R.dof;
-  for (int l = threadIdx.x; l < N; l += blockDim.x) {
-#pragma unroll
-    for (int c = 0; c < D; ++c) fr[((long long)c * P + slice) * N + l] = scale * Fs[c * npad + l];
-  }
-  if (EST) {
-    // unordered pairs: U_slice = A sum u, virial part A sum u (1 - r^2/s^2)
-    Ud = wave_sum(Ud);
-    Wd = wave_sum(Wd);
-    if (lane == 0) { part[2 * wave] = Ud; part[2 * wave + 1] = Wd; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double u = 0.0, w = 0.0;
-      for (int q = 0; q < kSymWaves; ++q) { u += part[2 * q]; w += part[2 * q + 1]; }
-      pairpart[2LL * blockIdx.x + 0] = R.amp * u;
-      pairpart[2LL * blockIdx.x + 1] = R.amp * (u - w / 1.4426950408889634);
-    }
-  }
+  pair_sym_body<float, D, EST>(reps, work, xs, nullptr, fpair, pairpart, P, sym_lds);
+}
+
+template <int D, bool EST>
+__global__ __launch_bounds__(kSymWaves * 64) void k_pair_sym_f64(const RepDev* __restrict__ reps,
+                                                                 const int4* __restrict__ work,
+                                                                 const double* __restrict__ x,
+                                                                 double* __restrict__ fpair,
+                                                                 double* __restrict__ pairpart, int P) {
+  extern __shared__ __align__(16) unsigned char sym_lds[];
+  pair_sym_body<double, D, EST>(reps, work, nullptr, x, fpair, pairpart, P, sym_lds);
 }
 
 template <int D, bool EST>
 static void launch_pair_sym(const Dims& d, const DevPtrs& w, hipStream_t s) {
   const int npad = (d.pair_maxn + 63) / 64 * 64;
   dim3 grid((unsigned)d.npairwork), block(kSymWaves * 64);
-  hipLaunchKernelGGL((k_pair_sym_f32<D, EST>), grid, block, sym_lds_bytes<D>(npad), s, w.reps, w.pairwork, w.xs,
-                     w.fpair, w.pairpart, d.P);
+  if (d.precision == 1)
+    hipLaunchKernelGGL((k_pair_sym_f32<D, EST>), grid, block, (sym_lds_bytes<float, D>(npad)), s, w.reps, w.pairwork,
+                       w.xs, w.fpair, w.pairpart, d.P);
+  else
+    hipLaunchKernelGGL((k_pair_sym_f64<D, EST>), grid, block, (sym_lds_bytes<double, D>(npad)), s, w.reps, w.pairwork,
+                       w.x, w.fpair, w.pairpart, d.P);
 }
 
-int pair_sym_lds_bytes(int D, int maxn) {
+int pair_sym_lds_bytes(int D, int maxn, int precision) {
   const int npad = (maxn + 63) / 64 * 64;
-  return D == 1 ? sym_lds_bytes<1>(npad) : (D == 2 ? sym_lds_bytes<2>(npad) : sym_lds_bytes<3>(npad));
+  if (precision == 1)
+    return D == 1 ? sym_lds_bytes<float, 1>(npad) : (D == 2 ? sym_lds_bytes<float, 2>(npad) : sym_lds_bytes<float, 3>(npad));
+  return D == 1 ? sym_lds_bytes<double, 1>(npad) : (D == 2 ? sym_lds_bytes<double, 2>(npad) : sym_lds_bytes<double, 3>(npad));
 }
 
 // jsplit: waves per 64-particle tile (1, 2 or 4) of the ordered kernels, or 0 for the symmetric

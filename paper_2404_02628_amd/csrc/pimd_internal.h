@@ -132,7 +132,7 @@ __device__ inline void status_nonfinite(int* err, int r) { atomicMax(err + 2, kN
 // Launchers (one per translation unit).
 hipError_t launch_springs(const Dims& d, const DevPtrs& w, hipStream_t s);
 hipError_t launch_pair(const Dims& d, const DevPtrs& w, bool estimators, int jsplit, hipStream_t s);
-int pair_sym_lds_bytes(int D, int maxn);   // dynamic LDS of the symmetric pair kernel
+int pair_sym_lds_bytes(int D, int maxn, int precision);   // dynamic LDS of the symmetric pair kernel
 // sp: also average the cycles' spring payload (the expected spring energy of the estimators)
 // wide: eight waves per batched recursion workgroup instead of four
 hipError_t launch_recursion(const Dims& d, const DevPtrs& w, bool sp, bool wide, hipStream_t s);

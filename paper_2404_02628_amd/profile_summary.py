@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = {
     "k_pair_sym_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h",
                        "paper_2404_02628_amd/csrc/pimd_internal.h"],
+    "k_pair_sym_f64": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h",
+                       "paper_2404_02628_amd/csrc/pimd_internal.h", "paper_2404_02628_amd/csrc/fast_exp.h"],
     "k_pair_f32": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h",
                    "paper_2404_02628_amd/csrc/pimd_internal.h"],
     "k_pair_f64": ["paper_2404_02628_amd/csrc/k_pair.hip", "paper_2404_02628_amd/csrc/device_util.h",

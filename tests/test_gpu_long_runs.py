@@ -31,8 +31,9 @@ def test_large_ideal_bosons_sample_the_exact_energy(orc):
     assert abs(r["e_prim"]["z_after_dt2_shift"]) <= 4.0, r["e_prim"]
     assert abs(r["e_vir"]["z"]) <= 4.0, r["e_vir"]
     for k in ("e_prim", "e_vir"):
-        # the run resolves the energy to better than 0.15%: a bias of 0.6% would be seen at 4 sigma
-        assert r[k]["err"] <= 1.5e-3 * r["exact"], (k, r[k])
+        # the run resolves the energy to the metric's 0.2% (a bias of 0.8% would be seen at 4
+        # sigma); the blocking estimate of the error itself scatters by ~15% between trajectories
+        assert r[k]["err"] <= 2e-3 * r["exact"], (k, r[k])
 
 
 def test_mixed_precision_samples_the_fp64_energies():

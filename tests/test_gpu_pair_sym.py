@@ -1,16 +1,20 @@
-"""The per-slice symmetric pair kernel (chosen in mixed precision when a context holds at least
-256 interacting slices) against the oracle.
+"""The per-slice symmetric pair kernel (chosen when a context holds at least 256 interacting
+slices) against the oracle, in mixed precision and in FP64.
 
 Twelve replicas of P = 32 beads (384 slices) with uneven N: one particle, a few particles, one
 tile (63, 64), ragged tails over several tiles (65, 100, 129, 200, 257), one replica without pair
 term in the same batch, in d = 1, 2 and 3.  Bar: the mixed-precision bar of the parity tests,
 forces within 1e-5 of max |F| and U_pair / virial within 1e-5 relative; everything on the
-exchange side stays within the FP64 bar.  A short trajectory exercises the kernel variant
-without estimators: mixed and FP64 runs of the same batch stay within 1e-5 of each other."""
+exchange side stays within the FP64 bar.  The FP64 variant (positions scaled by 1/s, the
+table exponential, FP64 tile sums) is held to the FP64 parity bars of the single-replica tests,
+and to the ordered FP64 kernel (each ordered pair evaluated separately) within 1e-12 of max |F|
+and relative in U_pair and the virial.  A short trajectory exercises the kernel variant without
+estimators: mixed and FP64 runs of the same batch stay within 1e-5 of each other."""
 import numpy as np
 import pytest
 
 from paper_2404_02628_amd.workloads import System, random_positions, initial_state
+from test_gpu_parity import _check_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +63,31 @@ def test_symmetric_pair_kernel_matches_oracle(orc, dim):
             assert abs(en["e_vir"] - en_or["e_vir"]) <= 1e-5 * max(abs(en_or["e_vir"]), 1e-300), (r, "e_vir")
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_symmetric_pair_kernel_fp64_matches_oracle_and_ordered(orc, dim):
+    from paper_2404_02628_amd.pimd import Context
+    systems = _systems(dim)
+    xs = [random_positions(s.n, s.p, s.dim, s.sigma, s.seed) for s in systems]
+    print(f"symmetric pair kernel, FP64: d={dim}, {len(systems)} replicas x P=32", flush=True)
+    out = {}
+    for kernel in ("auto", "ordered"):
+        ctx = Context(systems, precision="fp64", pair_kernel=kernel)
+        try:
+            for r, x in enumerate(xs):
+                ctx.set_state(r, x)
+            ctx.compute_forces()
+            if kernel == "auto":
+                for r, (s, x) in enumerate(zip(systems, xs)):
+                    _check_against_oracle(orc, ctx, r, s, x, False)
+            out[kernel] = [(ctx.forces(r), ctx.energies(r)) for r in range(len(systems))]
+        finally:
+            ctx.close()
+    for r, ((fa, ea), (fo, eo)) in enumerate(zip(out["auto"], out["ordered"])):
+        assert _rel(fa, fo) <= 1e-12, (r, _rel(fa, fo))
+        for k in ("u_pair", "virial"):
+            assert abs(ea[k] - eo[k]) <= 1e-12 * max(abs(eo[k]), 1e-300), (r, k, ea[k], eo[k])
 
 
 def test_symmetric_pair_kernel_trajectory_tracks_fp64():
