@@ -47,6 +47,15 @@ __device__ inline double read_lane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// v of lane (lane & ~3) + K, i.e. lane K of each aligned group of four (DPP quad permutation).
+template <int K>
+__device__ inline double quad_lane(double v) {
+  constexpr int kCtrl = K | (K << 2) | (K << 4) | (K << 6);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Work item of workgroup b in a launch of n workgroups.  Workgroups are dealt round-robin over
 // the kXcds accelerator dies (b runs on die b mod kXcds, each die with its own L2); this gives
 // each die one contiguous range of work items, so items listed next to each other (the tiles of

@@ -370,9 +370,11 @@ __device__ inline void inblock_alpha(SH& sh, double* __restrict__ Am, int cur, i
 
 
 // Max-plus pass D_i = max(LB_i, max_{s<i} (alpha_{i,s} + D_s)) with each lane's row of alpha held
-// in registers (alpha_{i,s} = -inf for s >= i).  Four rows per round: the in-group coefficients
-// come from the lanes that own those rows, and after the round's update `run` equals D on every
-// lane of the group, so at the end run_i = D_i.
+// in registers (alpha_{i,s} = -inf for s >= i).  Four rows per round, rows s0..s0+3 being one
+// aligned group of four lanes: within the group each row's value becomes final in turn and is
+// passed to the later rows of the group by a quad permutation (each lane uses its own row's
+// coefficients), then the four finished values are read out once and every later row takes
+// them, so at the end run_i = D_i.
 __device__ inline double maxplus_regs(const double* __restrict__ Am, double run) {
   const int lane = threadIdx.x & 63;
   double a[kTile];
@@ -380,14 +382,12 @@ __device__ inline double maxplus_regs(const double* __restrict__ Am, double run)
   for (int s = 0; s < kTile; ++s) a[s] = Am[s * kTile + lane];
 #pragma unroll
   for (int s0 = 0; s0 < kTile; s0 += 4) {
-    const double m10 = read_lane(a[s0], s0 + 1);
-    const double m20 = read_lane(a[s0], s0 + 2), m21 = read_lane(a[s0 + 1], s0 + 2);
-    const double m30 = read_lane(a[s0], s0 + 3), m31 = read_lane(a[s0 + 1], s0 + 3);
-    const double m32 = read_lane(a[s0 + 2], s0 + 3);
-    const double d0 = read_lane(run, s0);
-    const double d1 = fmax(read_lane(run, s0 + 1), m10 + d0);
-    const double d2 = fmax(fmax(read_lane(run, s0 + 2), m20 + d0), m21 + d1);
-    const double d3 = fmax(fmax(fmax(read_lane(run, s0 + 3), m30 + d0), m31 + d1), m32 + d2);
+    double c = run;   // final on lane s0 + k once columns s0..s0+k-1 are in
+    c = fmax(c, a[s0] + quad_lane<0>(c));
+    c = fmax(c, a[s0 + 1] + quad_lane<1>(c));
+    c = fmax(c, a[s0 + 2] + quad_lane<2>(c));
+    const double d0 = read_lane(c, s0), d1 = read_lane(c, s0 + 1);
+    const double d2 = read_lane(c, s0 + 2), d3 = read_lane(c, s0 + 3);
     run = fmax(fmax(run, a[s0] + d0), a[s0 + 1] + d1);
     run = fmax(fmax(run, a[s0 + 2] + d2), a[s0 + 3] + d3);
   }
@@ -395,9 +395,9 @@ __device__ inline double maxplus_regs(const double* __restrict__ Am, double run)
 }
 
 // Forward substitution w_i = acc_i + sum_{s<i} c_{i,s} w_s with each lane's row of c held in
-// registers (c_{i,s} = 0 for s >= i).  Four rows per round: their in-group coefficients come
-// from the lanes that own those rows, and after the round's update acc equals w on every lane
-// of the group, so at the end acc_i = w_i.
+// registers (c_{i,s} = 0 for s >= i), four rows per round as in maxplus_regs: the group's rows are
+// finished in turn through quad permutations, read out once, and every row takes them; the
+// multiply-adds run in the same order for every row, so at the end acc_i = w_i.
 __device__ inline double substitute_regs(const double* __restrict__ Am, double acc) {
   const int lane = threadIdx.x & 63;
   double c[kTile];
@@ -405,14 +405,12 @@ __device__ inline double substitute_regs(const double* __restrict__ Am, double a
   for (int s = 0; s < kTile; ++s) c[s] = Am[s * kTile + lane];
 #pragma unroll
   for (int s0 = 0; s0 < kTile; s0 += 4) {
-    const double m10 = read_lane(c[s0], s0 + 1);
-    const double m20 = read_lane(c[s0], s0 + 2), m21 = read_lane(c[s0 + 1], s0 + 2);
-    const double m30 = read_lane(c[s0], s0 + 3), m31 = read_lane(c[s0 + 1], s0 + 3);
-    const double m32 = read_lane(c[s0 + 2], s0 + 3);
-    const double w0 = read_lane(acc, s0);
-    const double w1 = fma(m10, w0, read_lane(acc, s0 + 1));
-    const double w2 = fma(m21, w1, fma(m20, w0, read_lane(acc, s0 + 2)));
-    const double w3 = fma(m32, w2, fma(m31, w1, fma(m30, w0, read_lane(acc, s0 + 3))));
+    double v = acc;   // final on lane s0 + k once columns s0..s0+k-1 are in
+    v = fma(c[s0], quad_lane<0>(v), v);
+    v = fma(c[s0 + 1], quad_lane<1>(v), v);
+    v = fma(c[s0 + 2], quad_lane<2>(v), v);
+    const double w0 = read_lane(v, s0), w1 = read_lane(v, s0 + 1);
+    const double w2 = read_lane(v, s0 + 2), w3 = read_lane(v, s0 + 3);
     acc = fma(c[s0], w0, acc);
     acc = fma(c[s0 + 1], w1, acc);
     acc = fma(c[s0 + 2], w2, acc);
