@@ -4,6 +4,11 @@
 
 namespace pimd {
 
+// Index of this wavefront in its workgroup, in a scalar register: the compiler cannot tell
+// that threadIdx.x >> 6 is the same in every lane, and branches, loop bounds and addresses
+// derived from it would otherwise run on the vector ALU under exec masks.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // Sum over the 64 lanes of a wavefront, identical result in every lane.
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -21,7 +26,7 @@ __device__ inline double wave_max(double v) {
 // order), result valid in thread 0.  `lds` needs K * (blockDim.x / 64) doubles.
 template <int K>
 __device__ inline void block_sum(double (&v)[K], double* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id(), nw = blockDim.x >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
   if (lane == 0) {

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_pair_f32(const RepDev* __restrict__ rep
   const int4 wk = work[g];
   const RepDev& R = reps[wk.x];
   const int N = R.n, slice = wk.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int itile = wave / JS, jpart = wave % JS;
   const int i = wk.z + itile * 64 + lane;
   const float* xsl = xs + R.shadow + (long long)slice * R.npad * DP;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_pair_f64(const RepDev* __restrict__ rep
   const int4 wk = work[g];
   const RepDev& R = reps[wk.x];
   const int N = R.n, slice = wk.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int itile = wave / JS, jpart = wave % JS;
   const int i = wk.z + itile * 64 + lane;
   const double inv_s = 1.0 / R.width;
@@ -339,7 +339,8 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
   const int N = R.n, slice = wk.y, npad = R.npad;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the tournament's tile arithmetic (two modulos per tile pair) then runs on the scalar unit
+  const int lane = threadIdx.x & 63, wave = wave_id();
   double* Fs = reinterpret_cast<double*>(lds);                    // [D][npad]
   double* tab = Fs + (long long)D * npad;                          // [kTab] (FP64 only)
   T* pos = reinterpret_cast<T*>(tab + SymPrec<T>::kTab);           // [npad][DP]
