@@ -213,16 +213,20 @@ static void launch_pair_js(const Dims& d, const DevPtrs& w, int js, hipStream_t 
 // indexed by a and by b.  After the tile pair, a transpose through LDS sums the eight lanes
 // that share a particle (reduce-scatter: lane L = c0 + 8 k0 ends with the total of particle L of
 // tile I and of particle k0 + 8 c0 of tile J, which keeps the J side's reads on distinct banks),
-// and the totals are added to the slice's FP64 forces in LDS.  Tile pairs are scheduled as a
+// and the totals are added to the slice's forces in LDS.  Tile pairs are scheduled as a
 // round-robin tournament (circle method): within a round no two tile pairs share a tile, so
 // the LDS force updates need no atomics and their order is fixed (results are reproducible).
 // The diagonal tiles (I, I) run first with the pairs j <= i masked out.  Padding particles sit
 // at distinct far-away positions, so their terms underflow to exactly zero.
 //
 // Two precisions share this schedule.  Mixed (T = float): the FP32 shadow, pre-scaled so that a
-// term is exp2(-|dr|^2) (one v_exp_f32), tile sums in FP32.  FP64 (T = double): the positions
-// scaled by 1/s, a term is exp(-|dr|^2) by the table exponential (its table in LDS), everything
-// in FP64.
+// term is exp2(-|dr|^2) (one v_exp_f32), tile sums and the slice's force accumulators in FP32
+// (a particle's force adds one partial per tile, so at N = 1600 a sum of 25 partials: rounding
+// of order 1e-7 of the force, against the mixed mode's 1e-5 bar).  FP32 accumulators halve that
+// part of the LDS, so four workgroups fit a compute unit at N = 1600 (34.9 KB each, three beside
+// a batched recursion workgroup) instead of three; measured 3.4% less pair time in the step at
+// 128 replicas.  FP64 (T = double): the positions scaled by 1/s, a term is exp(-|dr|^2) by the
+// table exponential (its table in LDS), everything in FP64.
 constexpr int kSymWaves = 4;
 constexpr int kRedStride = 9;   // LDS row stride of the per-wave transpose (conflict-free reads)
 
@@ -241,12 +245,12 @@ template <> struct SymPrec<double> {
 template <class T, int D>
 __host__ __device__ inline int sym_lds_bytes(int npad) {
   constexpr int DP = SymPrec<T>::template dp<D>();
-  return npad * (DP * (int)sizeof(T) + D * 8) + kSymWaves * 64 * kRedStride * (int)sizeof(T) + 2 * kSymWaves * 8 * 2 +
+  return npad * (DP + D) * (int)sizeof(T) + kSymWaves * 64 * kRedStride * (int)sizeof(T) + 2 * kSymWaves * 8 * 2 +
          SymPrec<T>::kTab * 8;
 }
 
 template <class T, int D, bool EST, bool DIAG>
-__device__ inline void sym_tile_pair(const T* __restrict__ pos, double* __restrict__ Fs, T* __restrict__ red,
+__device__ inline void sym_tile_pair(const T* __restrict__ pos, T* __restrict__ Fs, T* __restrict__ red,
                                      const double* __restrict__ tab, int npad, int I, int J, double& Ud, double& Wd) {
   constexpr int DP = SymPrec<T>::template dp<D>();
   const int lane = threadIdx.x & 63;
@@ -302,8 +306,8 @@ __device__ inline void sym_tile_pair(const T* __restrict__ pos, double* __restri
     T sj = T(0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) sj += red[(q + 8 * k0) * kRedStride + c0];
-    Fs[c * npad + I * 64 + lane] += (double)si;
-    Fs[c * npad + J * 64 + k0 + 8 * c0] += (double)sj;
+    Fs[c * npad + I * 64 + lane] += si;
+    Fs[c * npad + J * 64 + k0 + 8 * c0] += sj;
   }
 }
 
@@ -341,8 +345,8 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
   const int N = R.n, slice = wk.y, npad = R.npad;
   // the tournament's tile arithmetic (two modulos per tile pair) then runs on the scalar unit
   const int lane = threadIdx.x & 63, wave = wave_id();
-  double* Fs = reinterpret_cast<double*>(lds);                    // [D][npad]
-  double* tab = Fs + (long long)D * npad;                          // [kTab] (FP64 only)
+  T* Fs = reinterpret_cast<T*>(lds);                                   // [D][npad]
+  double* tab = reinterpret_cast<double*>(Fs + (long long)D * npad);  // [kTab] (FP64 only)
   T* pos = reinterpret_cast<T*>(tab + SymPrec<T>::kTab);           // [npad][DP]
   T* red = pos + (long long)npad * DP + wave * 64 * kRedStride;
   double* part = reinterpret_cast<double*>(pos + (long long)npad * DP + kSymWaves * 64 * kRedStride);
@@ -350,7 +354,7 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
   sym_load_slice<T, D>(pos, R, xs, x, slice, P);
   for (int l = threadIdx.x; l < npad; l += blockDim.x) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) Fs[c * npad + l] = 0.0;
+    for (int c = 0; c < D; ++c) Fs[c * npad + l] = T(0);
   }
   __syncthreads();
   const int T_ = npad / 64;
@@ -375,7 +379,7 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
   double* fr = fpair + R.dof;
   for (int l = threadIdx.x; l < N; l += blockDim.x) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) fr[((long long)c * P + slice) * N + l] = scale * Fs[c * npad + l];
+    for (int c = 0; c < D; ++c) fr[((long long)c * P + slice) * N + l] = scale * (double)Fs[c * npad + l];
   }
   if (EST) {
     // unordered pairs: U_slice = A sum u, virial part A sum u (1 - r^2/s^2)

@@ -1,8 +1,8 @@
 """The symmetric pair kernel at slice sizes that need more than 64 KiB of LDS per workgroup.
 
-gfx950 gives a workgroup up to 160 KiB of LDS, so the once-per-pair kernel now serves slices of
-up to 6,400 particles in 2-D and 3,840 in 3-D (it holds a slice's positions and FP64 forces in
-LDS).  Eight replicas of P = 32 make 256 interacting slices, so mixed precision selects it here.
+gfx950 gives a workgroup up to 160 KiB of LDS, so the once-per-pair kernel serves mixed-precision
+slices of up to 9,600 particles in 2-D and 5,504 in 3-D (it holds a slice's FP32 positions and
+FP32 force accumulators in LDS, 16 and 28 bytes per particle).  Eight replicas of P = 32 make 256 interacting slices, so mixed precision selects it here.
 The first and the last replica are compared with the CPU oracle at the mixed-precision bars
 (forces 1e-5 of the largest force, U_pair 1e-5), and every replica with the ordered kernel."""
 import numpy as np
@@ -13,7 +13,7 @@ from paper_2404_02628_amd.workloads import System, initial_state
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n,dim", [(3000, 2), (3800, 3)])
+@pytest.mark.parametrize("n,dim", [(4800, 2), (3800, 3)])
 def test_symmetric_kernel_beyond_64k_lds(orc, n, dim):
     from paper_2404_02628_amd.pimd import Context
     systems = [System(n=n, p=32, dim=dim, beta=3.0, xi=1.0, pair_amp=0.5, pair_width=0.5, sigma=2.0, seed=900 + r)
