@@ -296,16 +296,17 @@ __device__ inline void sym_tile_pair(const T* __restrict__ pos, T* __restrict__ 
   for (int c = 0; c < D; ++c) {
 #pragma unroll
     for (int a = 0; a < 8; ++a) red[lane * kRedStride + a] = Fi[a][c];
-    T si = T(0);
+    // (the sums start from their first element: 0 + x is not folded for floating point)
+    T si = red[c0 * kRedStride + k0];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) si += red[(c0 + 8 * k) * kRedStride + k0];
+    for (int k = 1; k < 8; ++k) si += red[(c0 + 8 * k) * kRedStride + k0];
 #pragma unroll
     for (int b = 0; b < 8; ++b) red[lane * kRedStride + b] = Fj[b][c];
     // lane (c0, k0) sums particle k0 + 8 c0 of tile J over the eight lanes that share k0 (rows
     // q + 8 k0, column c0: distinct banks across each half wave)
-    T sj = T(0);
+    T sj = red[8 * k0 * kRedStride + c0];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sj += red[(q + 8 * k0) * kRedStride + c0];
+    for (int q = 1; q < 8; ++q) sj += red[(q + 8 * k0) * kRedStride + c0];
     Fs[c * npad + I * 64 + lane] += si;
     Fs[c * npad + J * 64 + k0 + 8 * c0] += sj;
   }
