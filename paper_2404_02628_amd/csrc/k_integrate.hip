@@ -246,6 +246,7 @@ SyW sy_weights(int order) {
     double a = 1.0 / (4.0 - pow(4.0, 1.0 / 3.0));
     s.w[0] = a; s.w[1] = a; s.w[2] = 1.0 - 4.0 * a; s.w[3] = a; s.w[4] = a; s.n = 5;
   }
+  s.ec[0] = 1.0 / 5040.0; s.ec[1] = 1.0 / 720.0; s.ec[2] = 1.0 / 120.0; s.ec[3] = 1.0 / 24.0; s.ec[4] = 1.0 / 6.0;
   return s;
 }
 

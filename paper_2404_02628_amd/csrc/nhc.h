@@ -10,18 +10,24 @@
 
 namespace pimd {
 
-struct SyW { double w[5]; int n; };
+// Suzuki-Yoshida weights w[0..n-1], and the Taylor coefficients 1/7!, 1/6!, ..., 1/3! of
+// chain_exp.  The coefficients travel as kernel arguments so that they sit in scalar registers:
+// FP64 constants cannot be immediate operands, and kept in vector registers each one is first
+// copied into the accumulator of a two-operand multiply-add.
+struct SyW { double w[5]; double ec[5]; int n; };
 
 // exp(x) for the thermostat scale factors, whose arguments (h v / 4 and h v with h a fraction
 // of dt) are small: when every lane of the wavefront has |x| <= 1/32 the Taylor polynomial of
-// degree 7 (remainder below 3e-17 relative) replaces the library exponential (which the
-// wavefront then only runs for chains far from equilibrium).
-__device__ inline double chain_exp(double x) {
+// degree 7 (remainder below 3e-17 relative) replaces the library exponential.  The scale factors
+// of the chain elements, exp(-h v_{k+1} / 4), nearly always take the polynomial; the momentum's,
+// exp(-h v_1), takes the library exponential in most wavefronts (|h v_1| exceeds 1/32 in a few
+// percent of lanes at equilibrium).
+__device__ inline double chain_exp(double x, const double (&ec)[5]) {
   if (__all(fabs(x) <= 0.03125)) {
-    double q = fma(x, 1.0 / 5040.0, 1.0 / 720.0);
-    q = fma(q, x, 1.0 / 120.0);
-    q = fma(q, x, 1.0 / 24.0);
-    q = fma(q, x, 1.0 / 6.0);
+    double q = fma(x, ec[0], ec[1]);
+    q = fma(q, x, ec[2]);
+    q = fma(q, x, ec[3]);
+    q = fma(q, x, ec[4]);
     q = fma(q, x, 0.5);
     q = fma(q, x, 1.0);
     return fma(q, x, 1.0);
@@ -46,11 +52,11 @@ __device__ inline void nhc_propagate(double& p, double inv_mp, double& eta_sum, 
       v[M - 1] += 0.5 * h * Gm;
     }
     for (int k = M - 2; k >= 0; --k) {
-      sc[k] = chain_exp(-0.25 * h * v[k + 1]);
+      sc[k] = chain_exp(-0.25 * h * v[k + 1], sy.ec);
       double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
       v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];
     }
-    p *= chain_exp(-h * v[0]);
+    p *= chain_exp(-h * v[0], sy.ec);
     double vs = 0.0;
     for (int k = 0; k < M; ++k) vs += v[k];
     eta_sum = fma(h, vs, eta_sum);
