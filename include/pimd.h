@@ -86,7 +86,7 @@ typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
 #define PIMD_FLAG_PAIR_ORDERED 2  /* use the ordered pair kernel even where the symmetric
                                      per-slice kernel would be chosen (at least 256 interacting
                                      slices whose largest one fits the LDS of a compute unit:
-                                     N up to 9,600 in 2-D in mixed precision, 4,416 in FP64);
+                                     N up to 9,024 in 2-D in mixed precision, 4,416 in FP64);
                                      for tuning and testing */
 #define PIMD_FLAG_NO_PERSISTENT 4 /* run pimd_step with one launch per kernel and step even when
                                      every replica is small enough (N <= 64 and dim*P*N <= 512)

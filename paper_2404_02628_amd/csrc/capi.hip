@@ -43,8 +43,8 @@ const char* kKindNames[K_COUNT] = {"springs", "pair", "recursion", "exchange_for
                                    "persistent_steps"};
 
 // LDS one workgroup may hold on gfx950 (160 KiB per compute unit): the symmetric pair kernel keeps a
-// whole slice there, which bounds the N it serves (mixed: 9,600 particles in 2-D, 5,504 in 3-D,
-// 19,264 in 1-D; FP64: 4,416 in 2-D, 2,944 in 3-D, 8,896 in 1-D).
+// whole slice there, which bounds the N it serves (mixed: 9,024 particles in 2-D, 5,184 in 3-D,
+// 18,112 in 1-D; FP64: 4,416 in 2-D, 2,944 in 3-D, 8,896 in 1-D).
 constexpr int kMaxLdsBytes = 160 * 1024;
 
 // Steps per launch of the persistent kernel (a call with more steps is split).

@@ -223,21 +223,30 @@ static void launch_pair_js(const Dims& d, const DevPtrs& w, int js, hipStream_t 
 // term is exp2(-|dr|^2) (one v_exp_f32), tile sums and the slice's force accumulators in FP32
 // (a particle's force adds one partial per tile, so at N = 1600 a sum of 25 partials: rounding
 // of order 1e-7 of the force, against the mixed mode's 1e-5 bar).  FP32 accumulators halve that
-// part of the LDS, so four workgroups fit a compute unit at N = 1600 (34.9 KB each, three beside
-// a batched recursion workgroup) instead of three; measured 3.4% less pair time in the step at
-// 128 replicas.  FP64 (T = double): the positions scaled by 1/s, a term is exp(-|dr|^2) by the
+// part of the LDS (3.4% less pair time in the step at 128 replicas of N = 1600 than with FP64
+// accumulators).  FP64 (T = double): the positions scaled by 1/s, a term is exp(-|dr|^2) by the
 // table exponential (its table in LDS), everything in FP64.
-constexpr int kSymWaves = 4;
+//
+// Waves per workgroup (kWaves): wave w runs on SIMD w mod 4, and the waves of one SIMD together
+// take the tile pairs k = w (mod 4) of every round, so eight waves split a round's work over the
+// SIMDs exactly as four do, with two waves per SIMD to cover each other's latencies.  Mixed
+// precision uses eight (44.3 KB of LDS per workgroup at N = 1600: three per compute unit, two
+// beside a batched recursion workgroup; 2.8% less pair time in the step than four waves); FP64
+// keeps four, since its transpose buffer is twice as large and eight waves would halve the
+// workgroups per compute unit and the largest slice it serves.  Six waves would load two SIMDs
+// twice as much as the other two.
 constexpr int kRedStride = 9;   // LDS row stride of the per-wave transpose (conflict-free reads)
 
 template <class T> struct SymPrec;
 template <> struct SymPrec<float> {
   template <int D> static constexpr int dp() { return D == 3 ? 4 : D; }   // shadow row (float4 in 3-D)
+  static constexpr int kWaves = 8;
   static constexpr int kTab = 0;
   static __device__ inline float term(float r2, const double*) { return __builtin_amdgcn_exp2f(-r2); }
 };
 template <> struct SymPrec<double> {
   template <int D> static constexpr int dp() { return D; }
+  static constexpr int kWaves = 4;
   static constexpr int kTab = kExpTable;
   static __device__ inline double term(double r2, const double* tab) { return fast_exp_finite(-r2, tab); }
 };
@@ -245,8 +254,8 @@ template <> struct SymPrec<double> {
 template <class T, int D>
 __host__ __device__ inline int sym_lds_bytes(int npad) {
   constexpr int DP = SymPrec<T>::template dp<D>();
-  return npad * (DP + D) * (int)sizeof(T) + kSymWaves * 64 * kRedStride * (int)sizeof(T) + 2 * kSymWaves * 8 * 2 +
-         SymPrec<T>::kTab * 8;
+  constexpr int W = SymPrec<T>::kWaves;
+  return npad * (DP + D) * (int)sizeof(T) + W * 64 * kRedStride * (int)sizeof(T) + 2 * W * 8 + SymPrec<T>::kTab * 8;
 }
 
 template <class T, int D, bool EST, bool DIAG>
@@ -350,7 +359,8 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
   double* tab = reinterpret_cast<double*>(Fs + (long long)D * npad);  // [kTab] (FP64 only)
   T* pos = reinterpret_cast<T*>(tab + SymPrec<T>::kTab);           // [npad][DP]
   T* red = pos + (long long)npad * DP + wave * 64 * kRedStride;
-  double* part = reinterpret_cast<double*>(pos + (long long)npad * DP + kSymWaves * 64 * kRedStride);
+  constexpr int W = SymPrec<T>::kWaves;
+  double* part = reinterpret_cast<double*>(pos + (long long)npad * DP + W * 64 * kRedStride);   // [W][2]
   if constexpr (SymPrec<T>::kTab > 0) fill_exp_table(tab);
   sym_load_slice<T, D>(pos, R, xs, x, slice, P);
   for (int l = threadIdx.x; l < npad; l += blockDim.x) {
@@ -360,12 +370,12 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
   __syncthreads();
   const int T_ = npad / 64;
   double Ud = 0.0, Wd = 0.0;
-  for (int t = wave; t < T_; t += kSymWaves) sym_tile_pair<T, D, EST, true>(pos, Fs, red, tab, npad, t, t, Ud, Wd);
+  for (int t = wave; t < T_; t += W) sym_tile_pair<T, D, EST, true>(pos, Fs, red, tab, npad, t, t, Ud, Wd);
   __syncthreads();
   if (T_ > 1) {
     const int Tp = T_ + (T_ & 1), m = Tp - 1;
     for (int r = 0; r < m; ++r) {
-      for (int k = wave; k < Tp / 2; k += kSymWaves) {
+      for (int k = wave; k < Tp / 2; k += W) {
         const int p = k == 0 ? r : (r + k) % m;
         const int q = k == 0 ? m : (r - k + m) % m;
         if (p < T_ && q < T_) sym_tile_pair<T, D, EST, false>(pos, Fs, red, tab, npad, min(p, q), max(p, q), Ud, Wd);
@@ -391,7 +401,7 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
     __syncthreads();
     if (threadIdx.x == 0) {
       double u = 0.0, w = 0.0;
-      for (int q = 0; q < kSymWaves; ++q) { u += part[2 * q]; w += part[2 * q + 1]; }
+      for (int q = 0; q < W; ++q) { u += part[2 * q]; w += part[2 * q + 1]; }
       const double wscale = sizeof(T) == 4 ? 1.0 / 1.4426950408889634 : 1.0;
       pairpart[2LL * blockIdx.x + 0] = R.amp * u;
       pairpart[2LL * blockIdx.x + 1] = R.amp * (u - w * wscale);
@@ -400,7 +410,7 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
 }
 
 template <int D, bool EST>
-__global__ __launch_bounds__(kSymWaves * 64) void k_pair_sym_f32(const RepDev* __restrict__ reps,
+__global__ __launch_bounds__(SymPrec<float>::kWaves * 64) void k_pair_sym_f32(const RepDev* __restrict__ reps,
                                                                  const int4* __restrict__ work,
                                                                  const float* __restrict__ xs,
                                                                  double* __restrict__ fpair,
@@ -410,7 +420,7 @@ __global__ __launch_bounds__(kSymWaves * 64) void k_pair_sym_f32(const RepDev* _
 }
 
 template <int D, bool EST>
-__global__ __launch_bounds__(kSymWaves * 64) void k_pair_sym_f64(const RepDev* __restrict__ reps,
+__global__ __launch_bounds__(SymPrec<double>::kWaves * 64) void k_pair_sym_f64(const RepDev* __restrict__ reps,
                                                                  const int4* __restrict__ work,
                                                                  const double* __restrict__ x,
                                                                  double* __restrict__ fpair,
@@ -422,12 +432,12 @@ __global__ __launch_bounds__(kSymWaves * 64) void k_pair_sym_f64(const RepDev* _
 template <int D, bool EST>
 static void launch_pair_sym(const Dims& d, const DevPtrs& w, hipStream_t s) {
   const int npad = (d.pair_maxn + 63) / 64 * 64;
-  dim3 grid((unsigned)d.npairwork), block(kSymWaves * 64);
+  dim3 grid((unsigned)d.npairwork);
   if (d.precision == 1)
-    hipLaunchKernelGGL((k_pair_sym_f32<D, EST>), grid, block, (sym_lds_bytes<float, D>(npad)), s, w.reps, w.pairwork,
+    hipLaunchKernelGGL((k_pair_sym_f32<D, EST>), grid, dim3(SymPrec<float>::kWaves * 64), (sym_lds_bytes<float, D>(npad)), s, w.reps, w.pairwork,
                        w.xs, w.fpair, w.pairpart, d.P);
   else
-    hipLaunchKernelGGL((k_pair_sym_f64<D, EST>), grid, block, (sym_lds_bytes<double, D>(npad)), s, w.reps, w.pairwork,
+    hipLaunchKernelGGL((k_pair_sym_f64<D, EST>), grid, dim3(SymPrec<double>::kWaves * 64), (sym_lds_bytes<double, D>(npad)), s, w.reps, w.pairwork,
                        w.x, w.fpair, w.pairpart, d.P);
 }
 

@@ -1,8 +1,9 @@
 """The symmetric pair kernel at slice sizes that need more than 64 KiB of LDS per workgroup.
 
 gfx950 gives a workgroup up to 160 KiB of LDS, so the once-per-pair kernel serves mixed-precision
-slices of up to 9,600 particles in 2-D and 5,504 in 3-D (it holds a slice's FP32 positions and
-FP32 force accumulators in LDS, 16 and 28 bytes per particle).  Eight replicas of P = 32 make 256 interacting slices, so mixed precision selects it here.
+slices of up to 9,024 particles in 2-D and 5,184 in 3-D (it holds a slice's FP32 positions and
+FP32 force accumulators in LDS, 16 and 28 bytes per particle, beside eight waves' transpose
+buffers).  Eight replicas of P = 32 make 256 interacting slices, so mixed precision selects it here.
 The first and the last replica are compared with the CPU oracle at the mixed-precision bars
 (forces 1e-5 of the largest force, U_pair 1e-5), and every replica with the ordered kernel."""
 import numpy as np
