@@ -37,7 +37,7 @@ __device__ inline void integrate_one(const RepDev& R, int rep, long long gi, dou
   constexpr bool kChain = M > 0 && MODE != 2;
   if (kPair) fv = R.amp > 0.0 ? fv + fpv : fv;
   if (MODE == 0) {
-    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
+    if (M > 0) nhc_propagate<true>(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
     pv += hdt * fv;
     const double xn = xv + R.dt_mp * pv;
     if (!store) return;
@@ -53,11 +53,11 @@ __device__ inline void integrate_one(const RepDev& R, int rep, long long gi, dou
     }
     const double ftot = fv;
     pv += hdt * fv;
-    if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
+    if (M > 0) nhc_propagate<true>(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
     double xn = 0.0;
     if (MODE == 3) {
       // second thermostat half-step of this step and first of the next, chain in registers
-      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
+      if (M > 0) nhc_propagate<true>(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, sy);
       pv += hdt * fv;
       xn = xv + R.dt_mp * pv;
     }
@@ -246,7 +246,9 @@ SyW sy_weights(int order) {
     double a = 1.0 / (4.0 - pow(4.0, 1.0 / 3.0));
     s.w[0] = a; s.w[1] = a; s.w[2] = 1.0 - 4.0 * a; s.w[3] = a; s.w[4] = a; s.n = 5;
   }
-  s.ec[0] = 1.0 / 5040.0; s.ec[1] = 1.0 / 720.0; s.ec[2] = 1.0 / 120.0; s.ec[3] = 1.0 / 24.0; s.ec[4] = 1.0 / 6.0;
+  // 1/10!, 1/9!, ..., 1/3!
+  s.ec[0] = 1.0 / 3628800.0; s.ec[1] = 1.0 / 362880.0; s.ec[2] = 1.0 / 40320.0; s.ec[3] = 1.0 / 5040.0;
+  s.ec[4] = 1.0 / 720.0; s.ec[5] = 1.0 / 120.0; s.ec[6] = 1.0 / 24.0; s.ec[7] = 1.0 / 6.0;
   return s;
 }
 

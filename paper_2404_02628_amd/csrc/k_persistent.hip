@@ -287,14 +287,14 @@ __global__ __launch_bounds__(kPMaxDof) void k_persistent(PersistArgs A) {
     const long long stp = A.step0 + it + 1;
     const bool smp = A.sample_every > 0 && (stp % A.sample_every == 0);
     if (own) {
-      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy);
+      if (M > 0) nhc_propagate<false>(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy);
       pv += hdt * fv;
       xv += R.dt_mp * pv;
     }
     fv = persist_evaluate<D>(sh, R, P, t, own, ca, cj, cl, xv, smp, en);
     if (own) {
       pv += hdt * fv;
-      if (M > 0) nhc_propagate(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy);
+      if (M > 0) nhc_propagate<false>(pv, R.inv_mp, es, v, M, R.inv_q, R.kT, hdt, A.sy);
     }
     if (smp) {
       double kv[2] = {0.0, 0.0};

@@ -4,30 +4,48 @@
 // k_B T = 1/beta; NHC(tau) is the Suzuki-Yoshida factorised chain propagator of Martyna,
 // Tuckerman, Tobias and Klein (Mol. Phys. 87, 1117 (1996)) with one multiple-time-step cycle.
 // The streaming integrator and the persistent small-replica kernel both call it, so the two
-// paths apply the same arithmetic to every degree of freedom.
+// paths apply the same arithmetic to every degree of freedom, except that the streaming one may
+// take a wider polynomial tier for the momentum's scale factor where the other runs the library
+// exponential (results within an ulp or two of each other).
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace pimd {
 
-// Suzuki-Yoshida weights w[0..n-1], and the Taylor coefficients 1/7!, 1/6!, ..., 1/3! of
-// chain_exp.  The coefficients travel as kernel arguments so that they sit in scalar registers:
-// FP64 constants cannot be immediate operands, and kept in vector registers each one is first
-// copied into the accumulator of a two-operand multiply-add.
-struct SyW { double w[5]; double ec[5]; int n; };
+// Suzuki-Yoshida weights w[0..n-1], and the Taylor coefficients ec = 1/10!, 1/9!, ..., 1/3! of
+// the exponentials below.  The coefficients travel as kernel arguments so that they sit in scalar
+// registers: FP64 constants cannot be immediate operands, and kept in vector registers each one is
+// first copied into the accumulator of a two-operand multiply-add.
+struct SyW { double w[5]; double ec[8]; int n; };
 
 // exp(x) for the thermostat scale factors, whose arguments (h v / 4 and h v with h a fraction
-// of dt) are small: when every lane of the wavefront has |x| <= 1/32 the Taylor polynomial of
-// degree 7 (remainder below 3e-17 relative) replaces the library exponential.  The scale factors
-// of the chain elements, exp(-h v_{k+1} / 4), nearly always take the polynomial; the momentum's,
-// exp(-h v_1), takes the library exponential in most wavefronts (|h v_1| exceeds 1/32 in a few
-// percent of lanes at equilibrium).
-__device__ inline double chain_exp(double x, const double (&ec)[5]) {
-  if (__all(fabs(x) <= 0.03125)) {
+// of dt) are small.  Taylor polynomials replace the library exponential when every lane of the
+// wavefront is within their bound: degree 7 for |x| <= 1/32 (remainder below 3e-17 relative),
+// and, for the momentum's factor exp(-h v_1) in the streaming integrator, degree 10 for
+// |x| <= 1/8 (remainder below 1.2e-18): its argument exceeds 1/32 in a few percent of lanes at
+// equilibrium, so that nearly every wavefront of 64 degrees of freedom would otherwise run the
+// library exponential (fused integrator 320 -> 310 us at 128 replicas of N = 1600).
+__device__ inline double taylor_exp7(double x, const double (&ec)[8]) {
+  double q = fma(x, ec[3], ec[4]);
+  q = fma(q, x, ec[5]);
+  q = fma(q, x, ec[6]);
+  q = fma(q, x, ec[7]);
+  q = fma(q, x, 0.5);
+  q = fma(q, x, 1.0);
+  return fma(q, x, 1.0);
+}
+
+__device__ inline double chain_exp(double x, const double (&ec)[8]) {
+  if (__all(fabs(x) <= 0.03125)) return taylor_exp7(x, ec);
+  return exp(x);
+}
+
+__device__ inline double momentum_exp(double x, const double (&ec)[8]) {
+  if (__all(fabs(x) <= 0.03125)) return taylor_exp7(x, ec);
+  if (__all(fabs(x) <= 0.125)) {
     double q = fma(x, ec[0], ec[1]);
-    q = fma(q, x, ec[2]);
-    q = fma(q, x, ec[3]);
-    q = fma(q, x, ec[4]);
+#pragma unroll
+    for (int k = 2; k < 8; ++k) q = fma(q, x, ec[k]);
     q = fma(q, x, 0.5);
     q = fma(q, x, 1.0);
     return fma(q, x, 1.0);
@@ -41,6 +59,10 @@ __device__ inline double chain_exp(double x, const double (&ec)[5]) {
 // it is computed once per sub-step.  The chain positions eta_k only enter the conserved quantity
 // H' (through kT sum_k eta_k), so the propagator adds their increments h v_k into one number,
 // eta_sum, instead of keeping every eta_k.
+// kWide: the momentum's factor may take the degree-10 polynomial (the streaming integrator); the
+// persistent small-replica kernel, bound by its own instruction issue and whose small systems
+// nearly always stay within the degree-7 bound, runs without that tier (with it, 2% slower).
+template <bool kWide>
 __device__ inline void nhc_propagate(double& p, double inv_mp, double& eta_sum, double* v, int M, double inv_q,
                                      double kT, double tau, const SyW& sy) {
   const double kTq = kT * inv_q;
@@ -56,7 +78,7 @@ __device__ inline void nhc_propagate(double& p, double inv_mp, double& eta_sum, 
       double Gk = (k == 0) ? fma(p * p, inv_mp * inv_q, -kTq) : fma(v[k - 1], v[k - 1], -kTq);
       v[k] = (v[k] * sc[k] + 0.5 * h * Gk) * sc[k];
     }
-    p *= chain_exp(-h * v[0], sy.ec);
+    p *= kWide ? momentum_exp(-h * v[0], sy.ec) : chain_exp(-h * v[0], sy.ec);
     double vs = 0.0;
     for (int k = 0; k < M; ++k) vs += v[k];
     eta_sum = fma(h, vs, eta_sum);
