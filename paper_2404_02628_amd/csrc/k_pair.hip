@@ -230,7 +230,7 @@ static void launch_pair_js(const Dims& d, const DevPtrs& w, int js, hipStream_t 
 // Waves per workgroup (kWaves): wave w runs on SIMD w mod 4, and the waves of one SIMD together
 // take the tile pairs k = w (mod 4) of every round, so eight waves split a round's work over the
 // SIMDs exactly as four do, with two waves per SIMD to cover each other's latencies.  Mixed
-// precision uses eight (44.3 KB of LDS per workgroup at N = 1600: three per compute unit, two
+// precision uses eight (44.2 KB of LDS per workgroup at N = 1600: three per compute unit, two
 // beside a batched recursion workgroup; 2.8% less pair time in the step than four waves); FP64
 // keeps four, since its transpose buffer is twice as large and eight waves would halve the
 // workgroups per compute unit and the largest slice it serves.  Six waves would load two SIMDs
@@ -353,7 +353,8 @@ __device__ inline void pair_sym_body(const RepDev* __restrict__ reps, const int4
   const int4 wk = work[blockIdx.x];
   const RepDev& R = reps[wk.x];
   const int N = R.n, slice = wk.y, npad = R.npad;
-  // the tournament's tile arithmetic (two modulos per tile pair) then runs on the scalar unit
+  // with the wave index in a scalar register the tournament's tile arithmetic (two modulos per
+  // tile pair) runs on the scalar unit
   const int lane = threadIdx.x & 63, wave = wave_id();
   T* Fs = reinterpret_cast<T*>(lds);                                   // [D][npad]
   double* tab = reinterpret_cast<double*>(Fs + (long long)D * npad);  // [kTab] (FP64 only)

@@ -14,8 +14,9 @@ namespace pimd {
 
 // Suzuki-Yoshida weights w[0..n-1], and the Taylor coefficients ec = 1/10!, 1/9!, ..., 1/3! of
 // the exponentials below.  The coefficients travel as kernel arguments so that they sit in scalar
-// registers: FP64 constants cannot be immediate operands, and kept in vector registers each one is
-// first copied into the accumulator of a two-operand multiply-add.
+// registers: FP64 constants other than a few inline values (0.5, 1.0, ...) cannot be immediate
+// operands, and kept in vector registers each one is first copied into the accumulator of a
+// two-operand multiply-add.
 struct SyW { double w[5]; double ec[8]; int n; };
 
 // exp(x) for the thermostat scale factors, whose arguments (h v / 4 and h v with h a fraction
