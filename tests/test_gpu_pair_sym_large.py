@@ -46,3 +46,36 @@ def test_symmetric_kernel_beyond_64k_lds(orc, n, dim):
         assert float(np.max(np.abs(f - f_or))) <= 1e-5 * float(np.max(np.abs(f_or))), r
         assert abs(en["u_pair"] - en_or["u_pair"]) <= 1e-5 * abs(en_or["u_pair"]), r
         assert abs(en["v_exch"] - en_or["v_exch"]) <= 1e-10 * abs(en_or["v_exch"]), r
+
+
+# The largest slices the symmetric kernel takes in mixed precision fill 162.9 KB of a compute
+# unit's 160 KiB of LDS (2-D: N = 9024, 3-D: N = 5184); one particle more and the context falls
+# back to the ordered kernel.  The symmetric kernel sums in another order than the ordered one, so
+# its forces differ from the ordered kernel's in the last FP32 bits, while the fallback reproduces
+# them exactly: that tells which kernel ran.  Eight replicas of P = 32 (256 slices), one force
+# evaluation, compared with the ordered kernel (itself held to the oracle by the parity tests).
+@pytest.mark.parametrize("n,dim,symmetric", [(9024, 2, True), (9025, 2, False), (5184, 3, True), (5185, 3, False)])
+def test_symmetric_kernel_at_its_lds_limit(n, dim, symmetric):
+    from paper_2404_02628_amd.pimd import Context
+    systems = [System(n=n, p=32, dim=dim, beta=3.0, xi=1.0, pair_amp=0.5, pair_width=0.5, sigma=3.0, seed=950 + r)
+               for r in range(8)]
+    xs = [initial_state(s)[0] for s in systems]
+    out = {}
+    for kernel in ("auto", "ordered"):
+        print(f"N={n} d={dim}: {kernel} pair kernel", flush=True)
+        ctx = Context(systems, precision="mixed", pair_kernel=kernel)
+        try:
+            for r, x in enumerate(xs):
+                ctx.set_state(r, x)
+            ctx.compute_forces()
+            out[kernel] = [(ctx.forces(r), ctx.energies(r)["u_pair"]) for r in (0, len(systems) - 1)]
+        finally:
+            ctx.close()
+    for (fa, ua), (fo, uo) in zip(out["auto"], out["ordered"]):
+        assert np.all(np.isfinite(fa)) and np.isfinite(ua)
+        if symmetric:
+            assert float(np.max(np.abs(fa - fo))) > 0.0, "the symmetric kernel was not chosen"
+            assert float(np.max(np.abs(fa - fo))) <= 2e-5 * float(np.max(np.abs(fo)))
+            assert abs(ua - uo) <= 2e-5 * abs(uo)
+        else:
+            assert np.array_equal(fa, fo) and ua == uo, "the ordered kernel was not chosen"
