@@ -204,6 +204,47 @@ def test_short_trajectory_matches_oracle(orc, persistent):
     assert abs(nhc[-1] - float(np.sum(eta))) <= 1e-8 * float(np.sum(np.abs(eta)))
 
 
+@pytest.mark.parametrize("persistent", [True, False], ids=["persistent", "multi-kernel"])
+def test_trajectory_with_driven_thermostats_matches_oracle(orc, persistent):
+    """Thermostats far from rest: the first chain velocities are set so that the momentum's scale
+    factor exp(-h v_1) falls, wavefront by wavefront (64 degrees of freedom each), within
+    |h v_1| <= 1/32, within (1/32, 1/8] and beyond 1/8 -- the three ways the integrator evaluates
+    it (two polynomials and the library exponential).  Eight steps from that state against the
+    oracle's integrator, which evaluates every factor with the C library exp."""
+    from paper_2404_02628_amd.pimd import Context
+    s = System(n=8, p=12, dim=2, beta=3.0, xi=0.6, pair_amp=1.0, pair_width=0.5, sigma=0.5, seed=78)
+    x, p = initial_state(s)
+    m = 4
+    rng = np.random.default_rng(7)
+    veta = rng.normal(0.0, 0.5, (m,) + x.shape)
+    v1 = veta[0].reshape(-1)                      # dof order [dim][P][N], 192 dofs: three wavefronts
+    hmax = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0)) * 0.5 * s.dt   # largest Suzuki-Yoshida sub-step h (order 3)
+    hmin = abs(1.0 - 2.0 / (2.0 - 2.0 ** (1.0 / 3.0))) * 0.5 * s.dt
+    v1[:64] = rng.uniform(-0.5, 0.5, 64) * (1.0 / 32.0) / max(hmax, hmin)
+    v1[64:128] = rng.choice([-1.0, 1.0], 64) * rng.uniform(1.5, 3.0, 64) * (1.0 / 32.0) / min(hmax, hmin)
+    v1[64:128] = np.clip(v1[64:128], -0.9 * 0.125 / max(hmax, hmin), 0.9 * 0.125 / max(hmax, hmin))
+    v1[128:] = rng.choice([-1.0, 1.0], 64) * rng.uniform(2.0, 4.0, 64) * 0.125 / min(hmax, hmin)
+    nhc = np.concatenate([veta.reshape(-1), [0.0]])
+    ctx = Context([s], precision="fp64", nhc_len=m, persistent=persistent)
+    try:
+        ctx.set_state(0, x, p, nhc)
+        ctx.step(8, 0)
+        xg, pg, nhc_g = ctx.get_state(0)
+    finally:
+        ctx.close()
+    par = oracle_params(orc, s)
+    md = orc.OracleMD(dt=s.dt, nhc_len=m)
+    xo, po = x.copy(), p.copy()
+    f, _ = orc.compute_forces(par, xo)
+    eta = np.zeros((m,) + x.shape)
+    vo = veta.copy()
+    orc.step(par, md, xo, po, eta, vo, f, 8)
+    assert rel_max(xg, xo) <= 1e-10
+    assert rel_max(pg, po) <= 1e-10
+    assert rel_max(nhc_g[:-1].reshape(vo.shape), vo) <= 1e-10
+    assert abs(nhc_g[-1] - float(np.sum(eta))) <= 1e-10 * float(np.sum(np.abs(eta)))
+
+
 def test_conserved_quantity_and_density(orc):
     """H' stays flat along a thermostatted run; density counts cover every bead of every
     sample, and the last sample's histogram equals the oracle's histogram of the same beads."""
