@@ -71,9 +71,10 @@ typedef enum {
 
 typedef enum {
     PIMD_FP64 = 0,   /* every quantity in double precision                                   */
-    PIMD_MIXED = 1   /* pair distances, Gaussian terms and pair forces in FP32 (per-tile FP32
-                        partials folded into FP64); springs, recursions, probabilities,
-                        thermostat and all reductions in FP64                                  */
+    PIMD_MIXED = 1   /* pair distances, Gaussian terms and pair forces in FP32 (a particle's
+                        pair force summed in FP32 up to its slice total, then scaled in FP64);
+                        springs, recursions, probabilities, thermostat and all other
+                        reductions in FP64                                                   */
 } pimd_precision;
 
 typedef enum { PIMD_HOST = 0, PIMD_DEVICE = 1 } pimd_mem;
