@@ -15,7 +15,7 @@ Three checks of what the dynamics samples (Sec. IV.A compares PIMD energies with
 Per replica the time series gets a Flyvbjerg-Petersen blocking error; replicas are independent,
 so their means combine with the larger of the propagated error and the replica spread.
 
-``python tests/long_runs.py --check all --out gpurun_out/long_runs.md`` runs the full protocol
+``python tests/long_runs.py --check all --out <dir>/long_runs.md`` runs the full protocol
 (10^5 steps for the benchmark system) and writes a summary; the GPU tests run shortened versions.
 This is test infrastructure: it calls the CPU oracle for the exact energies.
 """
